@@ -1,0 +1,227 @@
+/*
+ * tlrqmc.h -- C ABI of the MI355X tile-low-rank quasi-Monte Carlo library.
+ *
+ * The library estimates multivariate normal and Student-t probabilities
+ * P(a <= X <= b) by the separation-of-variables (SOV) recursion run over
+ * many randomly shifted Richtmyer lattice points at once, with the Cholesky
+ * factor in tile-low-rank (TLR) form (Cao, Genton, Keyes, Turkiyyah,
+ * "Exploiting low rank covariance structures for computing high-dimensional
+ * normal and Student-t probabilities", arXiv 2003.11183).
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns an int status: 0 (TLRQMC_OK) on success, a
+ *    positive warning or a negative error code.  No C++ exception crosses
+ *    the ABI.  tlrqmc_last_error() returns a message for the last failure
+ *    on the calling thread.
+ *  - Host pointers are caller owned and only read during the call (outputs
+ *    are written during the call).  Objects returned through **out
+ *    (contexts, factors) are library owned until their _free/_destroy.
+ *  - Device memory is obtained from the context's allocator callback (or
+ *    hipMalloc when none is given); all device work is issued on the
+ *    context's HIP stream, and every call returns only after that work has
+ *    completed.
+ *  - Variables: a factor carries a permutation perm (perm[i] = original
+ *    index of the variable at integration position i).  Limits a, b are
+ *    always given in the caller's original order and are applied through
+ *    perm inside the library.  Limits are centred (the mean is subtracted
+ *    by the caller; the paper sets mu = 0 without loss of generality,
+ *    Section 2.1).  a_i = -inf and b_i = +inf are allowed.
+ *  - A context is not thread safe; use one context per thread.
+ */
+#ifndef TLRQMC_H
+#define TLRQMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  TLRQMC_OK = 0,
+  TLRQMC_WARN_RANKCAP = 1, /* a tile hit the rank cap: truncation above tol */
+  TLRQMC_PENDING = 2,      /* serving: the result is not ready yet          */
+  TLRQMC_EINVAL = -1,      /* invalid argument (message says which)         */
+  TLRQMC_ENOTSPD = -2,     /* covariance tile not positive definite         */
+  TLRQMC_ENOMEM = -3,      /* allocation failed                              */
+  TLRQMC_EDEVICE = -4,     /* HIP runtime error                              */
+  TLRQMC_ENOTFOUND = -5    /* serving: unknown ticket                        */
+};
+
+typedef struct tlrqmc_ctx tlrqmc_ctx;
+typedef struct tlrqmc_factor tlrqmc_factor;
+
+/* Device allocator: alloc returns device memory of at least `bytes` bytes
+ * (NULL on failure); free releases it.  Both are called on the thread that
+ * called into the library. */
+typedef struct {
+  void *(*alloc)(size_t bytes, void *user);
+  void (*free)(void *ptr, void *user);
+  void *user;
+} tlrqmc_allocator;
+
+/* Create a context on HIP device `device`, issuing work on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  `alloc` may be NULL. */
+int tlrqmc_ctx_create(int device, void *hip_stream, const tlrqmc_allocator *alloc,
+                      tlrqmc_ctx **out);
+void tlrqmc_ctx_destroy(tlrqmc_ctx *ctx);
+
+/* Message of the last failure on this thread ("" if none). */
+const char *tlrqmc_last_error(void);
+
+/* ---------------------------------------------------------------- setup --
+ * Covariance description (Section 3.2: the covariance comes from locations
+ * and a kernel).  kind 0: dense Sigma on the host, column-major with leading
+ * dimension ld >= n.  kind 1: exponential kernel
+ *   Sigma_pq = variance * exp(-|x_p - x_q| / range) + nugget * [p == q]
+ * on n locations xy (host, n x 2 row-major). */
+typedef struct {
+  int32_t kind;
+  int32_t reserved;
+  const double *sigma;
+  int64_t ld;
+  const double *xy;
+  double range;
+  double variance;
+  double nugget;
+} tlrqmc_cov;
+
+/* Geometric order of the variables (Section 3.2: index distance should
+ * follow spatial distance).  kind 1: Morton (Z-order) of the locations,
+ * quantised to 16 bits per axis over their bounding box, ties by index.
+ * kind 0: identity.  perm_out: n entries, caller allocated. */
+int tlrqmc_geometric_order(int64_t n, const tlrqmc_cov *cov, int32_t *perm_out);
+
+/* Block reordering (Section 3.3, "Block reordering" algorithm).  The blocks
+ * are consecutive size-m chunks of the geometric order.  Each block is
+ * scored with the univariate conditioning estimate of its probability
+ * Phi_m(a_l, b_l; Sigma_ll); blocks are then put in ascending score order by
+ * selection with swaps, and the variables inside each block take the order
+ * the univariate conditioning chose.  Ties go to the lowest index; a
+ * ragged last block stays last.  Host computation; ctx may be NULL.
+ * perm_out: n entries, caller allocated, perm_out[i] = original index. */
+int block_reorder(tlrqmc_ctx *ctx, int64_t n, const tlrqmc_cov *cov, const double *a,
+                  const double *b, int m, int32_t *perm_out);
+
+/* TLR Cholesky factor (Section 3.3; Section 3.4 defines B_i, U_ij, V_ij).
+ * Sigma is permuted by perm (NULL = geometric order), factored by a dense
+ * Cholesky on the device, and each off-diagonal m x m tile L_ij is replaced
+ * by U_ij V_ij^T keeping the singular values > tol (absolute 2-norm
+ * truncation, at most max_rank of them when max_rank > 0).  Returns
+ * TLRQMC_WARN_RANKCAP (factor still valid) when a tile needed more than
+ * max_rank, TLRQMC_ENOTSPD when Sigma is not positive definite (the message
+ * names the failing column). */
+int tlr_factor(tlrqmc_ctx *ctx, int64_t n, const tlrqmc_cov *cov, const int32_t *perm, int m,
+               double tol, int max_rank, tlrqmc_factor **out);
+
+/* Build a factor from host tiles (the exchange layout, also written by
+ * tlrqmc_factor_export).  r = ceil(n / m) tiles; tile i has m_i = min(m,
+ * n - i m) rows.
+ *   diag : the r diagonal tiles B_i, each m_i x m_i row-major, concatenated;
+ *          entries above the diagonal are ignored, the diagonal must be > 0.
+ *   ranks: r x r row-major, ranks[i*r+j] = k_ij >= 0 for i > j (others
+ *          ignored), k_ij <= min(m_i, m_j).
+ *   U, V : for i = 1..r-1, j = 0..i-1 (row-major order of the pairs):
+ *          U_ij (m_i x k_ij, row-major) and V_ij (m_j x k_ij, row-major),
+ *          concatenated; tile (i, j) of the factor is U_ij V_ij^T.
+ *   perm : n entries or NULL (identity).
+ * Errors: TLRQMC_EINVAL for bad sizes, a non-positive diagonal, a
+ * non-finite entry or an invalid permutation. */
+int tlrqmc_factor_import(tlrqmc_ctx *ctx, int64_t n, int m, const int32_t *perm,
+                         const double *diag, const int32_t *ranks, const double *U,
+                         const double *V, tlrqmc_factor **out);
+
+typedef struct {
+  int64_t n;
+  int32_t m, r;
+  int64_t k_tot;        /* sum of all ranks                          */
+  int32_t k_max;        /* largest rank                              */
+  int32_t cap_hits;     /* tiles truncated by the rank cap           */
+  int64_t diag_doubles; /* entries of the exchange diag array        */
+  int64_t uv_doubles;   /* entries of each exchange U and V array    */
+  int64_t device_bytes; /* device memory held by the factor          */
+} tlrqmc_factor_info;
+
+int tlrqmc_factor_stats(const tlrqmc_factor *f, tlrqmc_factor_info *out);
+
+/* Copy a factor to host arrays in the exchange layout of
+ * tlrqmc_factor_import (sizes from tlrqmc_factor_stats); any pointer may
+ * be NULL to skip that array. */
+int tlrqmc_factor_export(const tlrqmc_factor *f, int32_t *perm, double *diag, int32_t *ranks,
+                         double *U, double *V);
+
+void tlrqmc_factor_free(tlrqmc_factor *f);
+
+/* ------------------------------------------------------------ estimator --
+ * Quasi-Monte Carlo options.  Sample k = 1..n_samples of shift s =
+ * 0..n_shifts-1 uses the Richtmyer lattice point with generators
+ * frac(sqrt(p_{c+1})) (c = 0 the chi radius, c = 1..n the variables in
+ * integration order) shifted by the SplitMix64 stream of `seed`
+ * (Section 2.1, remark after the MVN algorithm; Section 3.4).
+ *   precision 0: FP64 everywhere.
+ *   precision 1: low-rank limit updates on BF16 MFMA with FP32
+ *                accumulation and a hi/lo split correction; diagonal tiles,
+ *                Phi, Phi^-1 and the log-space sums stay FP64.
+ *   logp_out  : optional host array of n_shifts * n_samples doubles that
+ *               receives log P of every sample (shift-major).
+ *   profile   : nonzero records HIP events around every kernel launch and
+ *               fills the kernel timing fields of the result.
+ *   chunk_samples: samples swept per pass (0 = as many as the device
+ *               memory budget allows; rounded up to a multiple of 256). */
+typedef struct {
+  int64_t n_samples;
+  int32_t n_shifts;
+  int32_t precision;
+  uint64_t seed;
+  double *logp_out;
+  int32_t profile;
+  int32_t reserved;
+  int64_t chunk_samples;
+} tlrqmc_qmc_opts;
+
+enum { TLRQMC_KERNEL_INIT = 0, TLRQMC_KERNEL_DELTA = 1, TLRQMC_KERNEL_SWEEP = 2,
+       TLRQMC_KERNEL_ZPROJ = 3, TLRQMC_KERNEL_REDUCE = 4, TLRQMC_KERNEL_KINDS = 5 };
+
+/* Estimate (Section 2.1; Section 4: relative error = standard error over
+ * mean).  log_p = log of the mean over shifts of the per-shift sample means;
+ * std_err = standard deviation of the shift means / sqrt(n_shifts);
+ * p = exp(log_p) (may underflow to 0).  n_dead counts samples whose
+ * integrand is exactly 0.  seconds: device time of the estimator (lattice,
+ * sweep, low-rank updates and reductions; setup excluded, as the paper
+ * times only the integration, Section 4). */
+typedef struct {
+  double log_p, p, std_err, rel_err;
+  double log_p_shift[64];
+  int64_t n_dead;
+  double seconds;
+  double kernel_seconds[TLRQMC_KERNEL_KINDS];
+  int64_t kernel_launches[TLRQMC_KERNEL_KINDS];
+  int32_t n_shifts;
+  int32_t chunks;
+} tlrqmc_result;
+
+/* MVN probability Phi_n(a, b; Sigma) (Section 2.1, Eq. 1-2; TLR recursion of
+ * Section 3.4).  a, b: host, n entries, original order.  n_samples >= 1,
+ * 2 <= n_shifts <= 64.  If a_i >= b_i for some i the result is log_p =
+ * -inf with status OK.  NaN limits -> TLRQMC_EINVAL. */
+int mvn_prob(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, const double *b,
+             const tlrqmc_qmc_opts *opts, tlrqmc_result *out);
+
+/* MVT probability T_n(a, b; Sigma, nu) with Sigma the scale matrix, as the
+ * chi scale mixture of Section 2.2, Eq. 4: each sample scales the limits by
+ * chi_nu^-1(w_0) / sqrt(nu) and runs the MVN recursion.  nu > 0. */
+int mvt_prob(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, const double *b,
+             double nu, const tlrqmc_qmc_opts *opts, tlrqmc_result *out);
+
+/* log P of samples k0 .. k0+count-1 (1-based) of shift `shift`, run through
+ * the same kernels as mvn_prob / mvt_prob (nu = 0 selects MVN).  logp_out:
+ * host, count entries. */
+int tlrqmc_sample_logp(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a,
+                       const double *b, double nu, const tlrqmc_qmc_opts *opts, int32_t shift,
+                       int64_t k0, int64_t count, double *logp_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TLRQMC_H */

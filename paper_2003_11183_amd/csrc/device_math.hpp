@@ -1,0 +1,331 @@
+// Device univariate functions of the SOV recursion (FP64).
+//
+// Phi and log Phi come from erfcx(z) = exp(z^2) erfc(z) (polynomial in
+// t = (z - K)/(z + K) up to z = 12, the asymptotic series above), so the
+// lower tail is formed as erfcx(|x|/sqrt2) exp(-x^2/2) / 2 with x^2 split
+// exactly by an fma; log Phi needs no exp.  Phi^-1(u) = sqrt2 x p(w) with
+// x = 2u - 1, w = -log(4 u (1 - u)) and p a polynomial in w or sqrt(w) on
+// five intervals (Giles' form of erfinv).  Coefficients: special_tables.hpp,
+// written by gen_special.py.  These keep the sweep kernel's register
+// footprint small enough for several waves per SIMD.
+//
+// The chi quantile of the Student-t radius is chi_nu^-1(u) = sqrt(2
+// P^-1(nu/2, u)) with P the regularized lower incomplete gamma function,
+// solved by Halley's method; P and Q = 1 - P come from the power series
+// (x < a + 1) and Legendre's continued fraction evaluated by the modified
+// Lentz algorithm otherwise.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#define TLRQMC_SPECIAL_TABLE static __constant__
+#include "special_tables.hpp"
+
+namespace tlrqmc {
+namespace dev {
+
+// Read-only global data seen through the constant address space: uniform
+// loads from it become scalar loads (one per wave, into SGPRs).
+#define TLRQMC_CONST __attribute__((address_space(4)))
+typedef const TLRQMC_CONST double *ctab_t;
+
+template <class T>
+__device__ __forceinline__ const TLRQMC_CONST T *as_const(const T *p) {
+  return (const TLRQMC_CONST T *)p;
+}
+
+// The coefficient table through a pointer the optimizer cannot see through:
+// the loads stay inside the loop that calls the function (one scalar load
+// per few coefficients) instead of being hoisted, which would pin all 134
+// coefficients in registers for the whole kernel.
+__device__ __forceinline__ ctab_t special_table() {
+  ctab_t p = (ctab_t)kSpecialTable;
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
+// Interval probabilities at or below this value are handled in log space.
+constexpr double kTiny = 1e-300;
+constexpr double kLogSqrt2Pi = 0.91893853320467274178;
+constexpr double kInvSqrtPi = 0.56418958354775628695;
+constexpr double kLog4 = 1.38629436111989061883;
+
+template <int OFF, int N>
+__device__ __forceinline__ double horner(ctab_t T, double s) {
+  double acc = T[OFF + N - 1];
+#pragma unroll
+  for (int i = N - 2; i >= 0; --i) acc = fma(acc, s, T[OFF + i]);
+  return acc;
+}
+
+constexpr double kLn2Hi = 6.93147180559945286227e-01;
+constexpr double kLn2Lo = 2.31904681384629955842e-17;
+
+// exp(x) for x <= 0: x = k ln2 + r with |r| <= ln2/2 (Cody-Waite split of
+// ln2), a polynomial for exp(r), then the exponent by ldexp.
+__device__ __forceinline__ double exp_nonpos(ctab_t T, double x) {
+  if (!(x > -745.2)) return x != x ? x : 0.0;
+  const double k = rint(x * M_LOG2E);
+  const double r = fma(-k, kLn2Lo, fma(-k, kLn2Hi, x));
+  return ldexp(horner<kOffExp, kNExp>(T, r * kExpH), static_cast<int>(k));
+}
+
+// log(x) for x > 0: x = m 2^e with m in [sqrt(1/2), sqrt 2), f = m - 1
+// (exact), s = f / (2 + f), log m = 2s + s^3 Q(s^2).
+__device__ __forceinline__ double log_pos(ctab_t T, double x) {
+  if (!(x > 0.0) || isinf(x)) return x == 0.0 ? -INFINITY : (x > 0.0 ? x : NAN);
+  int e;
+  double m = frexp(x, &e);
+  if (m < M_SQRT1_2) {
+    m *= 2.0;
+    e -= 1;
+  }
+  const double f = m - 1.0;
+  const double s = f / (2.0 + f);
+  const double v = s * s;
+  const double lm = fma(s * v, horner<kOffLog, kNLog>(T, (v - kLogC) * kLogH), 2.0 * s);
+  const double de = static_cast<double>(e);
+  return fma(de, kLn2Hi, fma(de, kLn2Lo, lm));
+}
+
+// log(1 + x) for x > -1: log of the rounded sum, corrected by its error.
+__device__ __forceinline__ double log1p_t(ctab_t T, double x) {
+  const double u = 1.0 + x;
+  return log_pos(T, u) + (x - (u - 1.0)) / u;
+}
+
+// erfcx(z) for z >= 0 (z = +inf gives 0).
+__device__ inline double erfcx_pos(ctab_t T, double z) {
+  if (z <= kErfcxZmax) {
+    const double t = (z - kErfcxK) / (z + kErfcxK);
+    const double g = horner<kOffErfcx, kNErfcx>(T, (t - kErfcxC) * kErfcxH);
+    return g * (1.0 - t) * 0.5;
+  }
+  // sum_k (-1)^k (2k-1)!! / (2 z^2)^k, divided by z sqrt(pi)
+  const double v = 0.5 / (z * z);
+  double acc = 0.0, coef = 1.0;
+  double pw = 1.0;
+#pragma unroll
+  for (int k = 0; k < kErfcxAsymTerms; ++k) {
+    acc = fma(coef, pw, acc);
+    pw *= v;
+    coef *= -(2.0 * k + 1.0);
+  }
+  return acc * kInvSqrtPi / z;
+}
+
+// q = Phi(-|x|) and lq = log q, for finite x.
+__device__ __forceinline__ void phi_lower(ctab_t T, double x, double &q, double &lq, double &ex) {
+  const double z = fabs(x) * M_SQRT1_2;
+  ex = 0.5 * erfcx_pos(T, z);
+  const double p = x * x;
+  const double a = 0.5 * p;
+  const double al = 0.5 * fma(x, x, -p);  // x^2 / 2 = a + al exactly
+  q = ex * exp_nonpos(T, -a) * (1.0 - al);
+  lq = log_pos(T, ex) - a - al;
+}
+
+__device__ inline double Phi(ctab_t T, double x) {
+  if (isinf(x)) return x > 0 ? 1.0 : 0.0;
+  double q, lq, ex;
+  phi_lower(T, x, q, lq, ex);
+  return x < 0.0 ? q : 1.0 - q;
+}
+
+__device__ inline double log_Phi(ctab_t T, double x) {
+  if (isinf(x)) return x > 0 ? 0.0 : -INFINITY;
+  double q, lq, ex;
+  phi_lower(T, x, q, lq, ex);
+  return x < 0.0 ? lq : log1p_t(T, -q);
+}
+
+// p(w) of Phi^-1 on the five intervals (s = sqrt(w) beyond the first).
+__device__ inline double inv_poly(ctab_t T, double wv) {
+  if (wv < 6.25) return horner<kOffInv1, kNInv1>(T, (wv - kInvC1) * kInvH1);
+  const double s = sqrt(wv);
+  if (s < 4.0) return horner<kOffInv2, kNInv2>(T, (s - kInvC2) * kInvH2);
+  if (s < 8.0) return horner<kOffInv3, kNInv3>(T, (s - kInvC3) * kInvH3);
+  if (s < 14.0) return horner<kOffInv4, kNInv4>(T, (s - kInvC4) * kInvH4);
+  return horner<kOffInv5, kNInv5>(T, (s - kInvC5) * kInvH5);
+}
+
+__device__ inline double Phi_inv(ctab_t T, double u) {
+  const double wv = -log_pos(T, 4.0 * u * (1.0 - u));
+  const double x = 2.0 * u - 1.0;
+  if (!(wv <= 756.25)) return u < 0.5 ? -INFINITY : INFINITY;  // u = 0 or 1
+  return M_SQRT2 * x * inv_poly(T, wv);
+}
+
+// Phi^-1(exp(lu)) for lu possibly far below the double range.
+__device__ inline double Phi_inv_log(ctab_t T, double lu) {
+  if (lu > -700.0) return Phi_inv(T, exp_nonpos(T, lu));
+  const double wv = -kLog4 - lu;  // -log(4 u (1 - u)) with 1 - u = 1
+  if (wv <= 756.25) return -M_SQRT2 * inv_poly(T, wv);
+  // Asymptotic start from log Phi(y) ~ -y^2/2 - log(-y) - log(2 pi)/2, then
+  // Newton steps on log Phi(y) - lu, whose derivative is phi(y) / Phi(y).
+  double y = -sqrt(-2.0 * lu - log(-4.0 * M_PI * lu));
+  for (int it = 0; it < 12; ++it) {
+    const double lp = log_Phi(T, y);
+    const double dy = (lp - lu) / exp(-0.5 * y * y - kLogSqrt2Pi - lp);
+    y -= dy;
+    if (fabs(dy) <= 1e-16 * fabs(y)) break;
+  }
+  return y;
+}
+
+__device__ __forceinline__ double log_add_exp(double x, double y) {
+  const double mx = fmax(x, y);
+  if (mx == -INFINITY) return -INFINITY;
+  return mx + log1p(exp(fmin(x, y) - mx));
+}
+
+// log(exp(x) - exp(y)) for x >= y.
+__device__ __forceinline__ double log_diff_exp(double x, double y) {
+  if (y == -INFINITY) return x;
+  return x + log1p(-exp(y - x));
+}
+
+// One variable of the recursion with conditional limits (ah, bh) and point
+// w: returns log(Phi(bh) - Phi(ah)) and sets y to the conditional quantile
+// Phi^-1(Phi(ah) + w (Phi(bh) - Phi(ah))).  Where ah > 0 the complement
+// CDFs are used; tiny intervals go through log Phi; an empty interval
+// gives -inf and y = 0.
+__device__ inline double sov_step(double ah, double bh, double w, double &y) {
+  ctab_t T = special_table();
+  const bool lower = ah <= 0.0;
+  const double lo = lower ? ah : -bh;
+  const double hi = lower ? bh : -ah;
+  const double d = Phi(T, lo);
+  const double e = Phi(T, hi);
+  const double delta = e - d;
+  double ld, yy;
+  if (delta > kTiny) {
+    const double u = lower ? fma(w, delta, d) : fma(-w, delta, e);
+    yy = Phi_inv(T, u);
+    ld = log_pos(T, delta);
+  } else {
+    const double l_lo = log_Phi(T, lo);
+    const double l_hi = log_Phi(T, hi);
+    ld = (l_hi > l_lo) ? log_diff_exp(l_hi, l_lo) : -INFINITY;
+    if (!(ld > -INFINITY)) {
+      y = 0.0;
+      return -INFINITY;
+    }
+    const double lw = log_pos(T, w);
+    const double lu = lower ? log_add_exp(l_lo, lw + ld) : log_diff_exp(l_hi, lw + ld);
+    yy = Phi_inv_log(T, lu);
+  }
+  if (!(ld > -INFINITY)) {
+    y = 0.0;
+    return -INFINITY;
+  }
+  y = lower ? yy : -yy;
+  return ld;
+}
+
+// One-sided form (a = -inf): returns log Phi(bh), sets y = Phi^-1(w Phi(bh)).
+// One log serves both signs of bh: log(ex) - x^2/2 below zero, and
+// log(1 - q) corrected to log1p(-q) above.
+__device__ inline double sov_step_upper(double bh, double w, double &y) {
+  ctab_t T = special_table();
+  if (isinf(bh)) {
+    if (bh < 0) {
+      y = 0.0;
+      return -INFINITY;
+    }
+    y = Phi_inv(T, w);
+    return 0.0;
+  }
+  const double z = fabs(bh) * M_SQRT1_2;
+  const double ex = 0.5 * erfcx_pos(T, z);
+  const double p = bh * bh;
+  const double a = 0.5 * p;
+  const double al = 0.5 * fma(bh, bh, -p);
+  const double q = ex * exp_nonpos(T, -a) * (1.0 - al);
+  const bool neg = bh < 0.0;
+  const double e = neg ? q : 1.0 - q;
+  const double arg = neg ? ex : e;
+  const double L = log_pos(T, arg);
+  // e >= 1/2 above zero, so (2 - e) stands in for 1/e in the correction,
+  // which is itself below one ulp of 1.
+  const double le = neg ? L - a - al : fma((-q) - (e - 1.0), 2.0 - e, L);
+  if (e > kTiny) {
+    y = Phi_inv(T, w * e);
+  } else {
+    y = Phi_inv_log(T, log_pos(T, w) + le);
+  }
+  return le;
+}
+
+// Regularized incomplete gamma: returns P(a, x) and sets q = Q(a, x).
+__device__ inline double gamma_pq(double a, double x, double lgam, double &q) {
+  if (x <= 0.0) {
+    q = 1.0;
+    return 0.0;
+  }
+  const double lpre = a * log(x) - x - lgam;
+  if (x < a + 1.0) {
+    double ap = a, term = 1.0 / a, sum = term;
+    for (int i = 0; i < 600; ++i) {
+      ap += 1.0;
+      term *= x / ap;
+      sum += term;
+      if (fabs(term) < fabs(sum) * 1e-17) break;
+    }
+    const double p = sum * exp(lpre);
+    q = 1.0 - p;
+    return p;
+  }
+  // Legendre continued fraction for Q by the modified Lentz algorithm.
+  const double tiny = 1e-300;
+  double bb = x + 1.0 - a, c = 1.0 / tiny, dd = 1.0 / bb, h = dd;
+  for (int i = 1; i < 600; ++i) {
+    const double an = -i * (i - a);
+    bb += 2.0;
+    dd = an * dd + bb;
+    if (fabs(dd) < tiny) dd = tiny;
+    c = bb + an / c;
+    if (fabs(c) < tiny) c = tiny;
+    dd = 1.0 / dd;
+    const double del = dd * c;
+    h *= del;
+    if (fabs(del - 1.0) < 1e-16) break;
+  }
+  q = exp(lpre) * h;
+  return 1.0 - q;
+}
+
+// Quantile of the chi distribution with nu degrees of freedom.
+__device__ inline double chi_inv(double nu, double u) {
+  const double a = 0.5 * nu;
+  const double lgam = lgamma(a);
+  // Wilson-Hilferty start, or the small-x power law when that is not positive.
+  const double z = Phi_inv(special_table(), u);
+  const double t = 1.0 / (9.0 * a);
+  double x = 1.0 - t + z * sqrt(t);
+  x = a * x * x * x;
+  const double xs = exp((log(u) + lgamma(a + 1.0)) / a);
+  if (!(x > 0.0) || xs < x * 0.5) x = fmax(xs, 1e-300);
+  const bool upper = u > 0.5;
+  const double target = upper ? 1.0 - u : u;
+  for (int it = 0; it < 100; ++it) {
+    double q;
+    const double p = gamma_pq(a, x, lgam, q);
+    const double f = upper ? target - q : p - target;  // P(x) - u either way
+    const double dens = exp((a - 1.0) * log(x) - x - lgam);
+    if (!(dens > 0.0)) break;
+    const double tn = f / dens;
+    const double dx = tn / (1.0 - 0.5 * tn * ((a - 1.0) / x - 1.0));
+    double xn = x - dx;
+    if (xn <= 0.0) xn = 0.5 * x;
+    if (fabs(xn - x) <= 1e-15 * x) {
+      x = xn;
+      break;
+    }
+    x = xn;
+  }
+  return sqrt(2.0 * x);
+}
+
+}  // namespace dev
+}  // namespace tlrqmc

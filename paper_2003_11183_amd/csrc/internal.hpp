@@ -1,0 +1,125 @@
+// Internal declarations of libtlrqmc: context, factor, kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "tlrqmc.h"
+
+namespace tlrqmc {
+
+// Thread-local error message; returns `code` for chaining.
+int fail(int code, const char *fmt, ...);
+void clear_error();
+
+// Row-block height of the diagonal-tile sweep and the padded row count of a
+// tile in the blocked layout.
+constexpr int kSweepBlock = 32;
+// Rows (delta) / columns (projection) produced per FP64 low-rank pass.
+constexpr int kLrRows = 64;
+
+inline int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
+
+}  // namespace tlrqmc
+
+struct tlrqmc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  tlrqmc_allocator alloc{};
+  bool has_alloc = false;
+  void *dmalloc(size_t bytes);
+  void dfree(void *p);
+};
+
+// Device-resident TLR factor.  Host vectors keep the exchange layout for
+// export and the sizes the launches need.
+struct tlrqmc_factor {
+  tlrqmc_ctx *ctx = nullptr;
+  int64_t n = 0;
+  int m = 0, r = 0;
+  std::vector<int32_t> perm;
+  std::vector<int> tm;          // rows of tile i
+  std::vector<int64_t> toff;    // first variable of tile i
+  std::vector<int32_t> rank;    // r x r, rank[i*r+j] for i > j
+  std::vector<int64_t> krow;    // sum_j<i k_ij: width of U_row(i)
+  std::vector<int64_t> kcol;    // sum_i>j k_ij: width of V_panel(j)
+  std::vector<int64_t> zoff;    // first Z row of tile i (prefix of krow)
+  int64_t k_tot = 0;
+  int k_max = 0;
+  int cap_hits = 0;
+  // Host exchange copies.
+  std::vector<double> h_diag, h_U, h_V;
+  // Device layouts.
+  double *d_diag = nullptr;     // blocked diagonal tiles (see kernels)
+  std::vector<int64_t> diag_off;
+  double *d_urow = nullptr;     // U_row(i): column-major, rows padded to kLrRows
+  std::vector<int64_t> urow_off;
+  std::vector<int> urow_ld;
+  double *d_vpan = nullptr;     // V_panel(j): row-major, columns padded to kLrRows
+  std::vector<int64_t> vpan_off;
+  std::vector<int> vpan_ld;
+  int32_t *d_zmap = nullptr;    // V_panel(j) column -> Z row
+  std::vector<int64_t> zmap_off;
+  uint64_t *d_gen = nullptr;    // lattice generators A_0..A_n
+  int64_t device_bytes = 0;
+};
+
+namespace tlrqmc {
+
+// ---- host lattice (lattice.cpp) ----
+std::vector<uint64_t> richtmyer_generators(int64_t dim);
+std::vector<uint64_t> splitmix64_table(uint64_t seed, int64_t count);
+
+// ---- factor construction (factor.cpp) ----
+int factor_build(tlrqmc_ctx *ctx, int64_t n, int m, const int32_t *perm, const double *diag,
+                 const int32_t *ranks, const double *U, const double *V, int cap_hits,
+                 tlrqmc_factor **out);
+
+// ---- kernels (kernels.hip) ----
+struct InitParams {
+  int64_t g0, count, N;
+  const uint64_t *A, *D;   // generators, shift table (ldD per shift)
+  int64_t ldD;
+  double nu;               // 0 = normal
+  double *logp;            // per chunk sample
+  double *R;               // per chunk sample (nu > 0)
+};
+
+struct SweepParams {
+  int64_t g0, count, N, ld, ldD;
+  int mj, c0;              // rows of the tile, lattice coordinate of row 0
+  const double *B;         // blocked tile
+  const double *a, *b;     // limits of the tile rows (a unused when one-sided)
+  const double *Delta;     // m x ld low-rank update, or null
+  const double *R;         // per chunk sample, or null
+  const uint64_t *A, *D;
+  double *logp;            // per chunk sample
+  double *Y;               // tile rows x ld
+};
+
+struct LrParams {
+  int64_t count, ld;
+  int rows, K;             // delta: rows = m_i, K = krow; zproj: rows = K_col, K = m_j
+  int lda;                 // padded leading dimension of the tile operand
+  const double *Mat;       // U_row (col-major, lda rows) or V_panel (row-major, lda cols)
+  const double *In;        // Z rows (delta) or Y (zproj), ld-strided
+  double *Out;             // Delta (delta) or Z (zproj)
+  const int32_t *map;      // zproj: output row map
+};
+
+struct ReduceParams {
+  int64_t N;
+  const double *logp;
+  double *part;            // per shift: max, sum exp(lp - max), dead count
+};
+
+void launch_init(hipStream_t s, const InitParams &p);
+void launch_sweep(hipStream_t s, const SweepParams &p, bool two_sided, bool scaled);
+void launch_delta_f64(hipStream_t s, const LrParams &p);
+void launch_zproj_f64(hipStream_t s, const LrParams &p);
+void launch_reduce(hipStream_t s, const ReduceParams &p, int n_shifts);
+
+}  // namespace tlrqmc

@@ -1,0 +1,241 @@
+// HIP kernels of the TLR QMC sweep (gfx950), FP64 form.
+//
+// One lane = one sample.  Samples of a chunk are laid out contiguously in
+// every per-sample buffer (Y, Delta, Z rows have leading dimension ld), so
+// each wave reads and writes 64 consecutive doubles.  Factor entries are
+// the same for every sample: their addresses depend only on loop counters
+// and kernel arguments, so they are fetched once per wave with scalar loads.
+//
+// Per diagonal tile j (Section 3.4, TLR QMC for MVN: the dense MVN step on
+// B_j after the limits of tile j were updated by the earlier tiles):
+//   k_delta_f64 : Delta_j = U_row(j) Z_row(j)   (low-rank limit update)
+//   k_sweep     : the SOV recursion over the rows of B_j (Section 2.1, Eq. 2)
+//   k_zproj_f64 : Z(:, j) = V_panel(j)^T Y_j    (rank-space image of y_j)
+// and k_reduce combines log P per shift (Section 2.1: mean over samples).
+#include "device_math.hpp"
+#include "internal.hpp"
+
+namespace tlrqmc {
+
+using namespace dev;
+
+__device__ __forceinline__ double lattice_point(uint64_t k, uint64_t A, uint64_t D) {
+  const uint64_t W = k * A + D;
+  return (static_cast<double>(W >> 12) + 0.5) * 0x1p-52;
+}
+
+// ---------------------------------------------------------------- init ----
+__global__ __launch_bounds__(256) void k_init(InitParams p) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= p.count) return;
+  const int64_t g = p.g0 + i;
+  p.logp[i] = 0.0;
+  if (p.nu > 0.0) {
+    const int64_t s = g / p.N;
+    const uint64_t k = static_cast<uint64_t>(g - s * p.N) + 1;
+    const double w0 = lattice_point(k, p.A[0], p.D[s * p.ldD]);
+    p.R[i] = chi_inv(p.nu, w0) / sqrt(p.nu);
+  }
+}
+
+// --------------------------------------------------------------- sweep ----
+// Blocked tile layout (row blocks of 32): for row block q the blocks
+// (q, 0..q) are stored consecutively, 1024 doubles each, starting at block
+// index q(q+1)/2.  An off-diagonal block (q, p) is column-major: entry
+// [u*32 + t] = B(32q + t, 32p + u).  The diagonal block is stored by
+// columns as well, entry [t*32 + i] = B(32q + t + i, 32q + t) for i >= 1
+// (zero past the block) and entry [t*32] = 1 / B(32q + t, 32q + t).
+//
+// Within a row block the recursion is right looking: acc[i] holds the
+// partial row sum of row t + i; after y_t is known the column below the
+// diagonal is added and the window slides down by one, so every index into
+// acc is a compile-time constant and acc stays in registers.
+template <bool TWO_SIDED, bool SCALED>
+__global__ __launch_bounds__(256) void k_sweep(SweepParams p) {
+  const int64_t si = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (si >= p.count) return;
+  const int64_t g = p.g0 + si;
+  const int64_t s = g / p.N;
+  const uint64_t k = static_cast<uint64_t>(g - s * p.N) + 1;
+  const uint64_t *Ds = p.D + s * p.ldD + p.c0;
+  const auto Ag = as_const(p.A + p.c0);
+  const auto bl = as_const(p.b);
+  const auto al = as_const(p.a);
+  const double R = SCALED ? p.R[si] : 1.0;
+  const int64_t ld = p.ld;
+  double *Y = p.Y + si;
+  const double *Dl = p.Delta ? p.Delta + si : nullptr;
+  double lp = p.logp[si];
+  const int nb = (p.mj + 31) >> 5;
+  auto blk = as_const(p.B);
+  for (int q = 0; q < nb; ++q) {
+    double acc[32];
+#pragma unroll
+    for (int t = 0; t < 32; ++t) acc[t] = 0.0;
+    for (int pb = 0; pb < q; ++pb, blk += 1024) {
+      const double *Yp = Y + static_cast<int64_t>(pb) * 32 * ld;
+#pragma unroll 4
+      for (int u = 0; u < 32; ++u) {
+        const double yv = Yp[u * ld];
+#pragma unroll
+        for (int t = 0; t < 32; ++t) acc[t] = fma(blk[u * 32 + t], yv, acc[t]);
+      }
+    }
+    const int rows = min(32, p.mj - q * 32);
+    for (int t = 0; t < rows; ++t) {
+      const int row = q * 32 + t;
+      const auto col = blk + t * 32;
+      double bt = R * bl[row];
+      if (Dl) bt -= Dl[row * ld];
+      const double w = lattice_point(k, Ag[row], Ds[row]);
+      double y, ldel;
+      if (TWO_SIDED) {
+        double at = R * al[row];
+        if (Dl) at -= Dl[row * ld];
+        ldel = sov_step((at - acc[0]) * col[0], (bt - acc[0]) * col[0], w, y);
+      } else {
+        ldel = sov_step_upper((bt - acc[0]) * col[0], w, y);
+      }
+      lp += ldel;
+      Y[row * ld] = y;
+#pragma unroll
+      for (int i = 1; i < 32; ++i) acc[i - 1] = fma(col[i], y, acc[i]);
+      acc[31] = 0.0;
+    }
+    blk += 1024;
+  }
+  p.logp[si] = lp;
+}
+
+// ------------------------------------------------------- low rank, FP64 ----
+// Delta(t, s) = sum_q U_row(t, q) Z(q, s) for 64 rows t per block row.
+// U_row is column-major with leading dimension lda (rows padded with zeros).
+__global__ __launch_bounds__(256) void k_delta_f64(LrParams p) {
+  const int64_t si = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (si >= p.count) return;
+  const int t0 = blockIdx.y * kLrRows;
+  double acc[kLrRows];
+#pragma unroll
+  for (int t = 0; t < kLrRows; ++t) acc[t] = 0.0;
+  const double *Z = p.In + si;
+  const auto U = as_const(p.Mat + t0);
+#pragma unroll 2
+  for (int q = 0; q < p.K; ++q) {
+    const double z = Z[static_cast<int64_t>(q) * p.ld];
+    const auto Uq = U + static_cast<int64_t>(q) * p.lda;
+#pragma unroll
+    for (int t = 0; t < kLrRows; ++t) acc[t] = fma(Uq[t], z, acc[t]);
+  }
+  double *O = p.Out + si;
+  const int nr = min(kLrRows, p.rows - t0);
+#pragma unroll
+  for (int t = 0; t < kLrRows; ++t)
+    if (t < nr) O[static_cast<int64_t>(t0 + t) * p.ld] = acc[t];
+}
+
+// Z(map(c), s) = sum_t V_panel(t, c) Y(t, s) for 64 columns c per block row.
+// V_panel is row-major with leading dimension lda (columns padded with zeros).
+__global__ __launch_bounds__(256) void k_zproj_f64(LrParams p) {
+  const int64_t si = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (si >= p.count) return;
+  const int c0 = blockIdx.y * kLrRows;
+  double acc[kLrRows];
+#pragma unroll
+  for (int c = 0; c < kLrRows; ++c) acc[c] = 0.0;
+  const double *Yv = p.In + si;
+  const auto V = as_const(p.Mat + c0);
+  const auto map = as_const(p.map);
+#pragma unroll 2
+  for (int t = 0; t < p.K; ++t) {
+    const double y = Yv[static_cast<int64_t>(t) * p.ld];
+    const auto Vt = V + static_cast<int64_t>(t) * p.lda;
+#pragma unroll
+    for (int c = 0; c < kLrRows; ++c) acc[c] = fma(Vt[c], y, acc[c]);
+  }
+  double *O = p.Out + si;
+  const int nc = min(kLrRows, p.rows - c0);
+#pragma unroll
+  for (int c = 0; c < kLrRows; ++c)
+    if (c < nc) O[static_cast<int64_t>(map[c0 + c]) * p.ld] = acc[c];
+}
+
+// -------------------------------------------------------------- reduce ----
+// One block per shift: max of log P, then sum of exp(log P - max) and the
+// count of empty samples, each lane striding in a fixed order and the lanes
+// combined by a fixed tree, so the result does not depend on scheduling.
+__global__ __launch_bounds__(256) void k_reduce(ReduceParams p) {
+  __shared__ double sh[256];
+  __shared__ double sd[256];
+  const int s = blockIdx.x;
+  const int t = threadIdx.x;
+  const double *lp = p.logp + static_cast<int64_t>(s) * p.N;
+  double mx = -INFINITY;
+  for (int64_t i = t; i < p.N; i += 256) mx = fmax(mx, lp[i]);
+  sh[t] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) sh[t] = fmax(sh[t], sh[t + w]);
+    __syncthreads();
+  }
+  mx = sh[0];
+  __syncthreads();
+  double sum = 0.0, dead = 0.0;
+  if (mx > -INFINITY) {
+    for (int64_t i = t; i < p.N; i += 256) {
+      const double v = lp[i];
+      sum += exp(v - mx);
+      dead += (v == -INFINITY) ? 1.0 : 0.0;
+    }
+  } else {
+    for (int64_t i = t; i < p.N; i += 256) dead += 1.0;
+  }
+  sh[t] = sum;
+  sd[t] = dead;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      sh[t] += sh[t + w];
+      sd[t] += sd[t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    p.part[3 * s + 0] = mx;
+    p.part[3 * s + 1] = sh[0];
+    p.part[3 * s + 2] = sd[0];
+  }
+}
+
+// ------------------------------------------------------------ launchers ----
+static inline unsigned grid_of(int64_t count) { return static_cast<unsigned>((count + 255) / 256); }
+
+void launch_init(hipStream_t s, const InitParams &p) {
+  hipLaunchKernelGGL(k_init, dim3(grid_of(p.count)), dim3(256), 0, s, p);
+}
+
+void launch_sweep(hipStream_t s, const SweepParams &p, bool two_sided, bool scaled) {
+  const dim3 grid(grid_of(p.count)), block(256);
+  if (two_sided) {
+    if (scaled) hipLaunchKernelGGL((k_sweep<true, true>), grid, block, 0, s, p);
+    else hipLaunchKernelGGL((k_sweep<true, false>), grid, block, 0, s, p);
+  } else {
+    if (scaled) hipLaunchKernelGGL((k_sweep<false, true>), grid, block, 0, s, p);
+    else hipLaunchKernelGGL((k_sweep<false, false>), grid, block, 0, s, p);
+  }
+}
+
+void launch_delta_f64(hipStream_t s, const LrParams &p) {
+  const dim3 grid(grid_of(p.count), static_cast<unsigned>((p.rows + kLrRows - 1) / kLrRows));
+  hipLaunchKernelGGL(k_delta_f64, grid, dim3(256), 0, s, p);
+}
+
+void launch_zproj_f64(hipStream_t s, const LrParams &p) {
+  const dim3 grid(grid_of(p.count), static_cast<unsigned>((p.rows + kLrRows - 1) / kLrRows));
+  hipLaunchKernelGGL(k_zproj_f64, grid, dim3(256), 0, s, p);
+}
+
+void launch_reduce(hipStream_t s, const ReduceParams &p, int n_shifts) {
+  hipLaunchKernelGGL(k_reduce, dim3(n_shifts), dim3(256), 0, s, p);
+}
+
+}  // namespace tlrqmc

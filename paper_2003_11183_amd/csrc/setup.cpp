@@ -1,0 +1,507 @@
+// Setup of the estimator (not on the timed path): geometric order, block
+// reordering and the TLR Cholesky factor.
+//
+// * Geometric order (Section 3.2): Morton order of the locations.
+// * Block reordering (Section 3.3, "Block reordering" algorithm): each block
+//   scored by univariate conditioning (Trinh and Genz 2015), blocks sorted
+//   ascending by selection with swaps, variables inside a block in the
+//   order the conditioning chose.
+// * TLR factor (Sections 3.3-3.4): dense Cholesky of the permuted
+//   covariance on the device (blocked right-looking: host POTRF of the
+//   diagonal block, rocBLAS TRSM and SYRK for the panel and the trailing
+//   matrix), then each off-diagonal tile truncated on the host to the
+//   singular values above tol: column-pivoted Householder QR (Businger and
+//   Golub 1965) down to a residual far below tol, then a one-sided Jacobi
+//   SVD (Hestenes 1958) of the small triangular factor.
+#include <rocblas/rocblas.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <numeric>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace tlrqmc {
+
+namespace {
+
+// ------------------------------------------------------------------ Morton
+uint64_t spread16(uint64_t v) {
+  v &= 0xFFFF;
+  uint64_t out = 0;
+  for (int bit = 0; bit < 16; ++bit) out |= ((v >> bit) & 1ull) << (2 * bit);
+  return out;
+}
+
+void morton(int64_t n, const double *xy, int32_t *perm) {
+  std::vector<uint64_t> key(n, 0);
+  for (int ax = 0; ax < 2; ++ax) {
+    double lo = INFINITY, hi = -INFINITY;
+    for (int64_t i = 0; i < n; ++i) {
+      lo = std::min(lo, xy[2 * i + ax]);
+      hi = std::max(hi, xy[2 * i + ax]);
+    }
+    for (int64_t i = 0; i < n; ++i) {
+      uint64_t qi = 0;
+      if (hi > lo) qi = static_cast<uint64_t>(std::floor((xy[2 * i + ax] - lo) / (hi - lo) * 65535.0 + 0.5));
+      key[i] |= ax == 0 ? (spread16(qi) << 1) : spread16(qi);
+    }
+  }
+  std::vector<int32_t> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) { return key[x] < key[y]; });
+  std::copy(idx.begin(), idx.end(), perm);
+}
+
+// Covariance entry (p, q) in original indexing.
+double cov_entry(const tlrqmc_cov *c, int64_t p, int64_t q) {
+  if (c->kind == 0) return c->sigma[q * c->ld + p];
+  const double dx = c->xy[2 * p] - c->xy[2 * q];
+  const double dy = c->xy[2 * p + 1] - c->xy[2 * q + 1];
+  double v = c->variance * std::exp(-std::sqrt(dx * dx + dy * dy) / c->range);
+  if (p == q) v += c->nugget;
+  return v;
+}
+
+int check_cov(int64_t n, const tlrqmc_cov *c) {
+  if (!c) return fail(TLRQMC_EINVAL, "null covariance");
+  if (c->kind == 0) {
+    if (!c->sigma || c->ld < n) return fail(TLRQMC_EINVAL, "dense covariance needs sigma and ld >= n");
+  } else if (c->kind == 1) {
+    if (!c->xy) return fail(TLRQMC_EINVAL, "kernel covariance needs locations");
+    if (!(c->range > 0.0) || !(c->variance > 0.0) || !(c->nugget >= 0.0))
+      return fail(TLRQMC_EINVAL, "range and variance must be > 0, nugget >= 0");
+    for (int64_t i = 0; i < 2 * n; ++i)
+      if (!std::isfinite(c->xy[i])) return fail(TLRQMC_EINVAL, "non-finite location");
+  } else {
+    return fail(TLRQMC_EINVAL, "unknown covariance kind %d", c->kind);
+  }
+  return TLRQMC_OK;
+}
+
+double Phi(double x) { return 0.5 * std::erfc(-x * M_SQRT1_2); }
+double phi(double x) { return std::isfinite(x) ? std::exp(-0.5 * x * x) * 0.39894228040143267794 : 0.0; }
+
+// Univariate conditioning of one block: chosen order and log of the score.
+double univariate_conditioning(int m, std::vector<double> &S, std::vector<double> &a, std::vector<double> &b,
+                               std::vector<int> &order) {
+  std::vector<double> L(static_cast<size_t>(m) * m, 0.0), y(m, 0.0);
+  order.resize(m);
+  std::iota(order.begin(), order.end(), 0);
+  auto Sat = [&](int i, int j) -> double & { return S[static_cast<size_t>(i) * m + j]; };
+  auto Lat = [&](int i, int j) -> double & { return L[static_cast<size_t>(i) * m + j]; };
+  double logp = 0.0;
+  std::vector<double> at(m), bt(m), sd(m), pr(m);
+  for (int i = 0; i < m; ++i) {
+    int best = i;
+    for (int j = i; j < m; ++j) {
+      double s = 0.0, v = Sat(j, j);
+      for (int k = 0; k < i; ++k) {
+        s += Lat(j, k) * y[k];
+        v -= Lat(j, k) * Lat(j, k);
+      }
+      sd[j] = std::sqrt(std::max(v, 0.0));
+      at[j] = (a[j] - s) / sd[j];
+      bt[j] = (b[j] - s) / sd[j];
+      pr[j] = Phi(bt[j]) - Phi(at[j]);
+      if (pr[j] < pr[best]) best = j;
+    }
+    if (best != i) {
+      for (int k = 0; k < m; ++k) std::swap(Sat(i, k), Sat(best, k));
+      for (int k = 0; k < m; ++k) std::swap(Sat(k, i), Sat(k, best));
+      for (int k = 0; k < m; ++k) std::swap(Lat(i, k), Lat(best, k));
+      std::swap(a[i], a[best]);
+      std::swap(b[i], b[best]);
+      std::swap(order[i], order[best]);
+      std::swap(at[i], at[best]);
+      std::swap(bt[i], bt[best]);
+      std::swap(sd[i], sd[best]);
+      std::swap(pr[i], pr[best]);
+    }
+    const double lii = sd[i];
+    Lat(i, i) = lii;
+    for (int j = i + 1; j < m; ++j) {
+      double s = Sat(j, i);
+      for (int k = 0; k < i; ++k) s -= Lat(j, k) * Lat(i, k);
+      Lat(j, i) = s / lii;
+    }
+    if (pr[i] > 0.0) {
+      y[i] = (phi(at[i]) - phi(bt[i])) / pr[i];
+      logp += std::log(pr[i]);
+    } else {
+      y[i] = std::isfinite(bt[i]) ? bt[i] : (std::isfinite(at[i]) ? at[i] : 0.0);
+      logp = -INFINITY;
+    }
+  }
+  return logp;
+}
+
+// ------------------------------------------------------- tile compression
+// Truncated SVD of the mi x mj column-major tile T (leading dimension ldt):
+// keeps the singular values > tol (at most cap when cap > 0).  Writes U
+// (mi x k, row-major, columns scaled by the singular values) and V
+// (mj x k, row-major); returns k and sets capped.
+int compress_tile(const double *T, int64_t ldt, int mi, int mj, double tol, int cap, std::vector<double> &U,
+                  std::vector<double> &V, bool &capped) {
+  capped = false;
+  std::vector<double> A(static_cast<size_t>(mi) * mj);
+  for (int c = 0; c < mj; ++c)
+    for (int rr = 0; rr < mi; ++rr) A[static_cast<size_t>(c) * mi + rr] = T[c * ldt + rr];
+  auto Aat = [&](int rr, int c) -> double & { return A[static_cast<size_t>(c) * mi + rr]; };
+  std::vector<int> piv(mj);
+  std::iota(piv.begin(), piv.end(), 0);
+  std::vector<double> cn(mj);
+  const int kmax = std::min(mi, mj);
+  std::vector<double> tau;
+  const double stop = 1e-3 * tol;
+  int kq = 0;
+  for (; kq < kmax; ++kq) {
+    double rest = 0.0;
+    int best = kq;
+    for (int c = kq; c < mj; ++c) {
+      double s = 0.0;
+      for (int rr = kq; rr < mi; ++rr) s += Aat(rr, c) * Aat(rr, c);
+      cn[c] = s;
+      rest += s;
+      if (s > cn[best]) best = c;
+    }
+    if (std::sqrt(rest) <= stop) break;
+    if (best != kq) {
+      for (int rr = 0; rr < mi; ++rr) std::swap(Aat(rr, kq), Aat(rr, best));
+      std::swap(piv[kq], piv[best]);
+    }
+    // Householder reflector for column kq, rows kq..mi-1
+    double nrm = 0.0;
+    for (int rr = kq; rr < mi; ++rr) nrm += Aat(rr, kq) * Aat(rr, kq);
+    nrm = std::sqrt(nrm);
+    const double alpha = Aat(kq, kq) >= 0 ? -nrm : nrm;
+    const double v0 = Aat(kq, kq) - alpha;
+    double vnorm2 = v0 * v0;
+    for (int rr = kq + 1; rr < mi; ++rr) vnorm2 += Aat(rr, kq) * Aat(rr, kq);
+    double t = 0.0;
+    if (vnorm2 > 0.0) {
+      t = 2.0 / vnorm2;
+      Aat(kq, kq) = v0;  // keep v in the column for now
+      for (int c = kq + 1; c < mj; ++c) {
+        double d = 0.0;
+        for (int rr = kq; rr < mi; ++rr) d += Aat(rr, kq) * Aat(rr, c);
+        d *= t;
+        for (int rr = kq; rr < mi; ++rr) Aat(rr, c) -= d * Aat(rr, kq);
+      }
+    }
+    tau.push_back(t);
+    // store v below the diagonal (scaled so v0 = 1), R diagonal = alpha
+    if (vnorm2 > 0.0) {
+      for (int rr = kq + 1; rr < mi; ++rr) Aat(rr, kq) /= v0;
+      tau.back() = t * v0 * v0;
+    }
+    Aat(kq, kq) = alpha;
+  }
+  const int kq_final = kq;
+  int k = 0;
+  std::vector<double> sig;
+  std::vector<double> Ur, Vr;
+  if (kq_final > 0) {
+    // G = R^T (mj x kq) in pivoted column order; one-sided Jacobi on its columns.
+    std::vector<double> G(static_cast<size_t>(mj) * kq_final, 0.0), J(static_cast<size_t>(kq_final) * kq_final, 0.0);
+    auto Gat = [&](int rr, int c) -> double & { return G[static_cast<size_t>(c) * mj + rr]; };
+    auto Jat = [&](int rr, int c) -> double & { return J[static_cast<size_t>(c) * kq_final + rr]; };
+    for (int c = 0; c < kq_final; ++c) {
+      Jat(c, c) = 1.0;
+      for (int col = c; col < mj; ++col) Gat(piv[col], c) = Aat(c, col);
+    }
+    for (int sweep = 0; sweep < 60; ++sweep) {
+      double off = 0.0;
+      for (int p = 0; p < kq_final - 1; ++p)
+        for (int q = p + 1; q < kq_final; ++q) {
+          double alpha = 0.0, beta = 0.0, gamma = 0.0;
+          for (int rr = 0; rr < mj; ++rr) {
+            alpha += Gat(rr, p) * Gat(rr, p);
+            beta += Gat(rr, q) * Gat(rr, q);
+            gamma += Gat(rr, p) * Gat(rr, q);
+          }
+          if (gamma == 0.0 || std::fabs(gamma) <= 1e-17 * std::sqrt(alpha * beta)) continue;
+          off = std::max(off, std::fabs(gamma) / std::sqrt(alpha * beta));
+          const double zeta = (beta - alpha) / (2.0 * gamma);
+          const double tt = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / std::sqrt(1.0 + tt * tt), sn = cs * tt;
+          for (int rr = 0; rr < mj; ++rr) {
+            const double gp = Gat(rr, p), gq = Gat(rr, q);
+            Gat(rr, p) = cs * gp - sn * gq;
+            Gat(rr, q) = sn * gp + cs * gq;
+          }
+          for (int rr = 0; rr < kq_final; ++rr) {
+            const double jp = Jat(rr, p), jq = Jat(rr, q);
+            Jat(rr, p) = cs * jp - sn * jq;
+            Jat(rr, q) = sn * jp + cs * jq;
+          }
+        }
+      if (off < 1e-15) break;
+    }
+    std::vector<std::pair<double, int>> sv(kq_final);
+    for (int c = 0; c < kq_final; ++c) {
+      double s = 0.0;
+      for (int rr = 0; rr < mj; ++rr) s += Gat(rr, c) * Gat(rr, c);
+      sv[c] = {std::sqrt(s), c};
+    }
+    std::sort(sv.begin(), sv.end(), [](const auto &x, const auto &y) {
+      return x.first > y.first || (x.first == y.first && x.second < y.second);
+    });
+    while (k < kq_final && sv[k].first > tol) ++k;
+    if (cap > 0 && k > cap) {
+      k = cap;
+      capped = true;
+    }
+    // Q (mi x kq) from the reflectors, applied to the chosen columns of J:
+    // U = Q J(:, idx) (times sigma), V = G(:, idx) / sigma.
+    U.assign(static_cast<size_t>(mi) * k, 0.0);
+    V.assign(static_cast<size_t>(mj) * k, 0.0);
+    std::vector<double> w(mi);
+    for (int c = 0; c < k; ++c) {
+      const int src = sv[c].second;
+      const double s = sv[c].first;
+      std::fill(w.begin(), w.end(), 0.0);
+      for (int rr = 0; rr < kq_final; ++rr) w[rr] = Jat(rr, src) * s;
+      for (int h = kq_final - 1; h >= 0; --h) {
+        if (tau[h] == 0.0) continue;
+        double d = w[h];
+        for (int rr = h + 1; rr < mi; ++rr) d += Aat(rr, h) * w[rr];
+        d *= tau[h];
+        w[h] -= d;
+        for (int rr = h + 1; rr < mi; ++rr) w[rr] -= d * Aat(rr, h);
+      }
+      for (int rr = 0; rr < mi; ++rr) U[static_cast<size_t>(rr) * k + c] = w[rr];
+      for (int rr = 0; rr < mj; ++rr) V[static_cast<size_t>(rr) * k + c] = Gat(rr, src) / s;
+    }
+  } else {
+    U.clear();
+    V.clear();
+  }
+  return k;
+}
+
+// Host Cholesky of an nb x nb column-major block in place; returns the
+// first failing column or -1.
+int host_potrf(double *A, int nb, int lda) {
+  for (int j = 0; j < nb; ++j) {
+    double d = A[static_cast<size_t>(j) * lda + j];
+    for (int k = 0; k < j; ++k) d -= A[static_cast<size_t>(k) * lda + j] * A[static_cast<size_t>(k) * lda + j];
+    if (!(d > 0.0)) return j;
+    d = std::sqrt(d);
+    A[static_cast<size_t>(j) * lda + j] = d;
+    for (int i = j + 1; i < nb; ++i) {
+      double s = A[static_cast<size_t>(j) * lda + i];
+      for (int k = 0; k < j; ++k) s -= A[static_cast<size_t>(k) * lda + i] * A[static_cast<size_t>(k) * lda + j];
+      A[static_cast<size_t>(j) * lda + i] = s / d;
+    }
+    for (int k = j + 1; k < nb; ++k) A[static_cast<size_t>(k) * lda + j] = 0.0;
+  }
+  return -1;
+}
+
+}  // namespace
+
+// Kernel building the permuted covariance (kernels_setup.hip).
+void launch_cov_exp(hipStream_t s, int64_t n, const double *xy_perm, double range, double variance,
+                    double nugget, double *A, int64_t lda, int64_t col0, int64_t ncols);
+
+}  // namespace tlrqmc
+
+using namespace tlrqmc;
+
+extern "C" {
+
+int tlrqmc_geometric_order(int64_t n, const tlrqmc_cov *cov, int32_t *perm_out) {
+  clear_error();
+  if (n < 1 || !perm_out) return fail(TLRQMC_EINVAL, "n must be >= 1 and perm_out non-null");
+  int st = check_cov(n, cov);
+  if (st) return st;
+  if (cov->kind == 1) morton(n, cov->xy, perm_out);
+  else std::iota(perm_out, perm_out + n, 0);
+  return TLRQMC_OK;
+}
+
+int block_reorder(tlrqmc_ctx *, int64_t n, const tlrqmc_cov *cov, const double *a, const double *b, int m,
+                  int32_t *perm_out) {
+  clear_error();
+  if (n < 1 || m < 1 || !a || !b || !perm_out) return fail(TLRQMC_EINVAL, "bad arguments to block_reorder");
+  int st = check_cov(n, cov);
+  if (st) return st;
+  for (int64_t i = 0; i < n; ++i)
+    if (std::isnan(a[i]) || std::isnan(b[i])) return fail(TLRQMC_EINVAL, "NaN limit at variable %lld", static_cast<long long>(i));
+  std::vector<int32_t> base(n);
+  if (cov->kind == 1) morton(n, cov->xy, base.data());
+  else std::iota(base.begin(), base.end(), 0);
+  const int64_t nblk = (n + m - 1) / m;
+  const int64_t nsort = (n % m == 0) ? nblk : nblk - 1;
+  std::vector<std::vector<int32_t>> blocks(nblk);
+  std::vector<double> score(nblk);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t q = 0; q < nblk; ++q) {
+    const int64_t i0 = q * m;
+    const int mb = static_cast<int>(std::min<int64_t>(m, n - i0));
+    std::vector<double> S(static_cast<size_t>(mb) * mb), al(mb), bl(mb);
+    for (int i = 0; i < mb; ++i) {
+      al[i] = a[base[i0 + i]];
+      bl[i] = b[base[i0 + i]];
+      for (int j = 0; j < mb; ++j) S[static_cast<size_t>(i) * mb + j] = cov_entry(cov, base[i0 + i], base[i0 + j]);
+    }
+    std::vector<int> order;
+    score[q] = univariate_conditioning(mb, S, al, bl, order);
+    blocks[q].resize(mb);
+    for (int i = 0; i < mb; ++i) blocks[q][i] = base[i0 + order[i]];
+  }
+  for (int64_t j = 0; j < nsort; ++j) {
+    int64_t best = j;
+    for (int64_t l = j + 1; l < nsort; ++l)
+      if (score[l] < score[best]) best = l;
+    if (best != j) {
+      std::swap(score[j], score[best]);
+      std::swap(blocks[j], blocks[best]);
+    }
+  }
+  int64_t o = 0;
+  for (auto &blk : blocks)
+    for (int32_t v : blk) perm_out[o++] = v;
+  return TLRQMC_OK;
+}
+
+int tlr_factor(tlrqmc_ctx *ctx, int64_t n, const tlrqmc_cov *cov, const int32_t *perm, int m, double tol,
+               int max_rank, tlrqmc_factor **out) {
+  clear_error();
+  if (!ctx || !out) return fail(TLRQMC_EINVAL, "null context or output");
+  *out = nullptr;
+  if (n < 1 || m < 1) return fail(TLRQMC_EINVAL, "n and m must be >= 1");
+  if (!(tol >= 0.0)) return fail(TLRQMC_EINVAL, "tol must be >= 0");
+  if (max_rank < 0) return fail(TLRQMC_EINVAL, "max_rank must be >= 0");
+  int st = check_cov(n, cov);
+  if (st) return st;
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(TLRQMC_EDEVICE, "hipSetDevice failed");
+  std::vector<int32_t> p(n);
+  if (perm) {
+    std::vector<uint8_t> seen(n, 0);
+    for (int64_t i = 0; i < n; ++i) {
+      if (perm[i] < 0 || perm[i] >= n || seen[perm[i]]) return fail(TLRQMC_EINVAL, "perm is not a permutation");
+      seen[perm[i]] = 1;
+      p[i] = perm[i];
+    }
+  } else if (cov->kind == 1) {
+    morton(n, cov->xy, p.data());
+  } else {
+    std::iota(p.begin(), p.end(), 0);
+  }
+  hipStream_t s = ctx->stream;
+  const int64_t lda = round_up(n, 64);
+  double *A = static_cast<double *>(ctx->dmalloc(static_cast<size_t>(lda) * n * sizeof(double)));
+  if (!A) return fail(TLRQMC_ENOMEM, "device allocation of the %lld x %lld covariance failed",
+                      static_cast<long long>(n), static_cast<long long>(n));
+  std::unique_ptr<double, std::function<void(double *)>> Aguard(A, [ctx](double *q) { ctx->dfree(q); });
+  // covariance in integration order, column-major
+  if (cov->kind == 1) {
+    std::vector<double> xyp(2 * n);
+    for (int64_t i = 0; i < n; ++i) {
+      xyp[2 * i] = cov->xy[2 * p[i]];
+      xyp[2 * i + 1] = cov->xy[2 * p[i] + 1];
+    }
+    double *dxy = static_cast<double *>(ctx->dmalloc(2 * n * sizeof(double)));
+    if (!dxy) return fail(TLRQMC_ENOMEM, "device allocation failed");
+    hipMemcpyAsync(dxy, xyp.data(), 2 * n * sizeof(double), hipMemcpyHostToDevice, s);
+    launch_cov_exp(s, n, dxy, cov->range, cov->variance, cov->nugget, A, lda, 0, n);
+    const hipError_t e = hipStreamSynchronize(s);
+    ctx->dfree(dxy);
+    if (e != hipSuccess) return fail(TLRQMC_EDEVICE, "covariance kernel failed");
+  } else {
+    std::vector<double> col(n);
+    for (int64_t j = 0; j < n; ++j) {
+      for (int64_t i = 0; i < n; ++i) col[i] = cov->sigma[static_cast<int64_t>(p[j]) * cov->ld + p[i]];
+      if (hipMemcpy(A + j * lda, col.data(), n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(TLRQMC_EDEVICE, "copy of the covariance failed");
+    }
+  }
+  // blocked right-looking Cholesky
+  rocblas_handle h;
+  if (rocblas_create_handle(&h) != rocblas_status_success) return fail(TLRQMC_EDEVICE, "rocblas_create_handle failed");
+  std::unique_ptr<_rocblas_handle, rocblas_status (*)(rocblas_handle)> hguard(h, rocblas_destroy_handle);
+  rocblas_set_stream(h, s);
+  const int nb = 256;
+  std::vector<double> blk(static_cast<size_t>(nb) * nb);
+  for (int64_t k0 = 0; k0 < n; k0 += nb) {
+    const int kb = static_cast<int>(std::min<int64_t>(nb, n - k0));
+    double *Akk = A + k0 * lda + k0;
+    if (hipMemcpy2DAsync(blk.data(), kb * sizeof(double), Akk, lda * sizeof(double), kb * sizeof(double), kb,
+                         hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail(TLRQMC_EDEVICE, "copy of a diagonal block failed");
+    const int bad = host_potrf(blk.data(), kb, kb);
+    if (bad >= 0)
+      return fail(TLRQMC_ENOTSPD, "covariance not positive definite at column %lld (tile %lld)",
+                  static_cast<long long>(k0 + bad), static_cast<long long>((k0 + bad) / m));
+    if (hipMemcpy2DAsync(Akk, lda * sizeof(double), blk.data(), kb * sizeof(double), kb * sizeof(double), kb,
+                         hipMemcpyHostToDevice, s) != hipSuccess)
+      return fail(TLRQMC_EDEVICE, "copy of a diagonal block failed");
+    const int64_t rest = n - k0 - kb;
+    if (rest > 0) {
+      const double one = 1.0, minus = -1.0;
+      double *P = A + k0 * lda + k0 + kb;
+      if (rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
+                        rocblas_diagonal_non_unit, static_cast<rocblas_int>(rest), kb, &one, Akk,
+                        static_cast<rocblas_int>(lda), P, static_cast<rocblas_int>(lda)) != rocblas_status_success ||
+          rocblas_dsyrk(h, rocblas_fill_lower, rocblas_operation_none, static_cast<rocblas_int>(rest), kb, &minus, P,
+                        static_cast<rocblas_int>(lda), &one, A + (k0 + kb) * lda + k0 + kb,
+                        static_cast<rocblas_int>(lda)) != rocblas_status_success)
+        return fail(TLRQMC_EDEVICE, "rocBLAS update failed");
+    }
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(TLRQMC_EDEVICE, "Cholesky failed on the device");
+  // tiles to the exchange layout, compressing the off-diagonal ones
+  const int r = static_cast<int>((n + m - 1) / m);
+  std::vector<int> tm(r);
+  for (int i = 0; i < r; ++i) tm[i] = static_cast<int>(std::min<int64_t>(m, n - static_cast<int64_t>(i) * m));
+  std::vector<int64_t> doff(r + 1, 0);
+  for (int i = 0; i < r; ++i) doff[i + 1] = doff[i] + static_cast<int64_t>(tm[i]) * tm[i];
+  std::vector<double> hdiag(doff[r]);
+  std::vector<int32_t> ranks(static_cast<size_t>(r) * r, 0);
+  std::vector<std::vector<double>> Us(static_cast<size_t>(r) * r), Vs(static_cast<size_t>(r) * r);
+  int cap_hits = 0;
+  std::vector<double> panel;
+  for (int j = 0; j < r; ++j) {
+    const int64_t c0 = static_cast<int64_t>(j) * m;
+    const int64_t rows = n - c0;
+    panel.resize(static_cast<size_t>(rows) * tm[j]);
+    if (hipMemcpy2D(panel.data(), rows * sizeof(double), A + c0 * lda + c0, lda * sizeof(double),
+                    rows * sizeof(double), tm[j], hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(TLRQMC_EDEVICE, "copy of the factor failed");
+    for (int t = 0; t < tm[j]; ++t)
+      for (int u = 0; u < tm[j]; ++u)
+        hdiag[doff[j] + static_cast<int64_t>(t) * tm[j] + u] = u <= t ? panel[static_cast<size_t>(u) * rows + t] : 0.0;
+    int hits = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : hits)
+    for (int i = j + 1; i < r; ++i) {
+      bool capped = false;
+      const double *T = panel.data() + (static_cast<int64_t>(i) * m - c0);
+      const int k = compress_tile(T, rows, tm[i], tm[j], tol, max_rank, Us[static_cast<size_t>(i) * r + j],
+                                  Vs[static_cast<size_t>(i) * r + j], capped);
+      ranks[static_cast<size_t>(i) * r + j] = k;
+      hits += capped ? 1 : 0;
+    }
+    cap_hits += hits;
+  }
+  Aguard.reset();
+  std::vector<double> hU, hV;
+  for (int i = 1; i < r; ++i)
+    for (int j = 0; j < i; ++j) {
+      const auto &u = Us[static_cast<size_t>(i) * r + j];
+      const auto &v = Vs[static_cast<size_t>(i) * r + j];
+      hU.insert(hU.end(), u.begin(), u.end());
+      hV.insert(hV.end(), v.begin(), v.end());
+    }
+  st = factor_build(ctx, n, m, p.data(), hdiag.data(), ranks.data(), hU.data(), hV.data(), cap_hits, out);
+  if (st) return st;
+  return cap_hits > 0 ? TLRQMC_WARN_RANKCAP : TLRQMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,236 @@
+"""GPU parity: the HIP path against the oracle on identical points.
+
+Every test feeds the same factor, limits, lattice and shifts to the library
+(through its C ABI) and to the oracle, and compares per-sample log P and the
+final estimate.  FP64 bar: |log P_gpu - log P_oracle| <= 1e-10 max(1, |log P|)
+per sample, i.e. 1e-10 relative on log P, or on P itself where |log P| < 1.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import factor as OF
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_2003_11183_amd import tlrqmc
+    return tlrqmc
+
+
+@pytest.fixture(scope="module")
+def ctx(T):
+    return T.Context(0)
+
+
+def assert_logp_close(got, ref, tol=TOL):
+    got, ref = np.asarray(got), np.asarray(ref)
+    assert got.shape == ref.shape
+    assert np.array_equal(np.isneginf(got), np.isneginf(ref))
+    fin = np.isfinite(ref)
+    assert np.all(np.isfinite(got[fin]))
+    err = np.abs(got[fin] - ref[fin]) / np.maximum(1.0, np.abs(ref[fin]))
+    assert err.max(initial=0.0) <= tol, f"max scaled error {err.max():.3e}"
+
+
+def assert_estimate_close(res, ref, tol=TOL):
+    assert abs(res["log_p"] - ref["log_p"]) <= tol * max(1.0, abs(ref["log_p"]))
+    assert abs(res["std_err"] - ref["std_err"]) <= 1e-8 * ref["std_err"] + 1e-300
+    assert np.allclose(res["log_p_shift"], ref["log_p_shift"], rtol=tol, atol=tol)
+
+
+def oracle_logp(fac, a_perm, b_perm, nu, seed, M, N, samples):
+    """Oracle log P for (shift, k) pairs, grouped by shift."""
+    out = np.empty(len(samples))
+    lat = oracle.api.Lattice(fac_n(fac), M, seed)
+    rows = oracle.api.rows_of(fac)
+    by_shift = {}
+    for idx, (s, k) in enumerate(samples):
+        by_shift.setdefault(s, []).append((idx, k))
+    for s, lst in by_shift.items():
+        ks = np.array([k for _, k in lst])
+        lp = oracle.sample_logp(rows, a_perm, b_perm, nu, seed, M, s, ks, lat)
+        for (idx, _), v in zip(lst, lp):
+            out[idx] = v
+    return out
+
+
+def fac_n(fac):
+    return sum(d.shape[0] for d in fac[0])
+
+
+def exp_factor(g, beta, m, tol, cap=0):
+    xy = synth.grid_xy(g)
+    perm = OF.morton_order(xy)
+    diag, ranks, U, V, hits = OF.tlr_factor(xy, beta, perm, m, tol, cap)
+    return (diag, ranks, U, V), perm, xy
+
+
+def run_both(T, ctx, fac, perm, a, b, nu, N, M, seed, chunk=0, samples=None):
+    n = fac_n(fac)
+    m = fac[0][0].shape[0]
+    F = T.Factor.from_tiles(ctx, n, m, fac[0], fac[1], fac[2], fac[3], perm)
+    res = T.probability(ctx, F, a, b, N, M, seed, nu=nu, return_logp=True, chunk=chunk)
+    ap, bp = np.asarray(a)[perm], np.asarray(b)[perm]
+    if samples is None:
+        ref, ref_logp = oracle.probability(fac, ap, bp, nu, N, M, seed)
+        return res, ref, res["logp"], ref_logp
+    got = np.array([res["logp"][s, k - 1] for (s, k) in samples])
+    return res, None, got, oracle_logp(fac, ap, bp, nu, seed, M, N, samples)
+
+
+# -------------------------------------------------------------- small cases
+
+def test_dense_single_tile_n256_full_estimate(T, ctx):
+    """The dense workload: 16 x 16 grid, range 0.1, b ~ U(0, 4), one tile."""
+    c = synth.config(1)
+    fac, perm, _ = exp_factor(16, c["beta"], 256, 0.0)
+    res, ref, lg, lr = run_both(T, ctx, fac, perm, c["a"], c["b"], 0.0, 10_000, 10, c["seed_shift"])
+    assert_logp_close(lg, lr)
+    assert_estimate_close(res, ref)
+
+
+@pytest.mark.parametrize("two_sided,nu", [(False, 0.0), (True, 0.0), (False, 7.0), (True, 5.0)])
+def test_random_tlr_ragged_chunked(T, ctx, two_sided, nu):
+    """Random TLR factor, n = 1000 (last tile 40 rows), several chunks."""
+    n, m = 1000, 64
+    fac = synth.random_tlr_factor(n, m, seed=31, rank_mean=5.0, rank_max=20)
+    rng = np.random.default_rng(4)
+    b = rng.uniform(0.0, 3.0, n)
+    a = np.where(rng.random(n) < 0.5, -np.inf, b - rng.uniform(0.5, 4.0, n)) if two_sided else np.full(n, -np.inf)
+    perm = rng.permutation(n).astype(np.int32)
+    res, ref, lg, lr = run_both(T, ctx, fac, perm, a, b, nu, 300, 3, 77, chunk=256)
+    assert res["chunks"] == 4
+    assert_logp_close(lg, lr)
+    assert_estimate_close(res, ref)
+
+
+def test_exp_kernel_tlr_factor_n1024(T, ctx):
+    fac, perm, _ = exp_factor(32, 0.1, 128, 1e-5)
+    b = synth.upper_limits_uniform(1024, 2005)
+    a = np.full(1024, -np.inf)
+    res, ref, lg, lr = run_both(T, ctx, fac, perm, a, b, 0.0, 1000, 4, 9)
+    assert_logp_close(lg, lr)
+    assert_estimate_close(res, ref)
+
+
+def test_sample_debug_entry_matches_full_run(T, ctx):
+    n, m = 300, 64
+    fac = synth.random_tlr_factor(n, m, seed=3)
+    b = np.linspace(0.1, 3.0, n)
+    a = np.full(n, -np.inf)
+    F = T.Factor.from_tiles(ctx, n, m, *fac)
+    full = T.probability(ctx, F, a, b, 500, 4, 123, nu=6.0, return_logp=True)
+    part = T.sample_logp(ctx, F, a, b, 6.0, 500, 4, 123, shift=2, k0=17, count=333)
+    assert np.array_equal(part, full["logp"][2, 16:16 + 333])
+
+
+def test_independent_variables_every_sample_exact(T, ctx):
+    """Diagonal factor: each sample equals the product of univariate probabilities."""
+    n, m = 200, 64
+    rng = np.random.default_rng(8)
+    sd = rng.uniform(0.5, 2.0, n)
+    sizes = [64, 64, 64, 8]
+    diag, o = [], 0
+    for s in sizes:
+        diag.append(np.diag(sd[o:o + s]))
+        o += s
+    ranks = np.zeros((4, 4), dtype=np.int32)
+    a = np.where(rng.random(n) < 0.3, -np.inf, rng.uniform(-2.0, 1.0, n))
+    b = np.where(rng.random(n) < 0.1, np.inf, np.maximum(a, -3.0) + rng.uniform(0.2, 3.0, n))
+    F = T.Factor.from_tiles(ctx, n, m, diag, ranks, {}, {})
+    res = T.probability(ctx, F, a, b, 256, 2, 5, return_logp=True)
+    want = 0.0
+    for i in range(n):
+        lo, hi = a[i] / sd[i], b[i] / sd[i]
+        if lo > 0:
+            p = 0.5 * math.erfc(lo / math.sqrt(2)) - 0.5 * math.erfc(hi / math.sqrt(2))
+        else:
+            p = 0.5 * math.erfc(-hi / math.sqrt(2)) - 0.5 * math.erfc(-lo / math.sqrt(2))
+        want += math.log(p)
+    assert np.allclose(res["logp"], want, rtol=1e-13, atol=0)
+    assert res["std_err"] <= 1e-13 * res["p"]
+
+
+def test_orthant_probability_tlr(T, ctx):
+    """rho = 1/2 orthant: P = 1/(n+1) exactly; TLR tiles of rank one."""
+    n, m = 512, 64
+    L = np.linalg.cholesky(0.5 * np.eye(n) + 0.5)
+    diag, ranks, U, V, _ = OF.tlr_from_dense(L, m, 1e-12)
+    F = T.Factor.from_tiles(ctx, n, m, diag, ranks, U, V)
+    res = T.probability(ctx, F, np.full(n, -np.inf), np.zeros(n), 20_000, 16, 1)
+    assert abs(res["p"] - 1.0 / (n + 1)) <= 3.0 * res["std_err"]
+
+
+def test_empty_interval_and_infinite_limits(T, ctx):
+    n, m = 100, 32
+    fac = synth.random_tlr_factor(n, m, seed=2)
+    F = T.Factor.from_tiles(ctx, n, m, *fac)
+    a = np.full(n, -np.inf)
+    b = np.full(n, 1.0)
+    b[7] = -np.inf
+    res = T.probability(ctx, F, a, b, 100, 2, 1)
+    assert res["log_p"] == -np.inf and res["p"] == 0.0
+    b = np.full(n, np.inf)
+    res = T.probability(ctx, F, a, b, 100, 2, 1, return_logp=True)
+    assert res["log_p"] == 0.0 and np.all(res["logp"] == 0.0)
+
+
+def test_repeat_runs_are_bitwise_identical(T, ctx):
+    n, m = 700, 64
+    fac = synth.random_tlr_factor(n, m, seed=12)
+    F = T.Factor.from_tiles(ctx, n, m, *fac)
+    b = np.linspace(0.5, 2.5, n)
+    r1 = T.probability(ctx, F, np.full(n, -np.inf), b, 1000, 5, 4, nu=7.0, return_logp=True)
+    r2 = T.probability(ctx, F, np.full(n, -np.inf), b, 1000, 5, 4, nu=7.0, return_logp=True)
+    assert np.array_equal(r1["logp"], r2["logp"]) and r1["log_p"] == r2["log_p"]
+
+
+def test_invalid_arguments(T, ctx):
+    n, m = 64, 32
+    fac = synth.random_tlr_factor(n, m, seed=2)
+    F = T.Factor.from_tiles(ctx, n, m, *fac)
+    b = np.ones(n)
+    for kw in (dict(N=0, M=4), dict(N=10, M=1), dict(N=10, M=65)):
+        with pytest.raises(T.TLRQMCError):
+            T.probability(ctx, F, np.full(n, -np.inf), b, kw["N"], kw["M"], 1)
+    bad = b.copy()
+    bad[3] = np.nan
+    with pytest.raises(T.TLRQMCError):
+        T.probability(ctx, F, np.full(n, -np.inf), bad, 10, 2, 1)
+    with pytest.raises(T.TLRQMCError):
+        T.Factor.from_tiles(ctx, n, m, [-fac[0][0], fac[0][1]], *fac[1:])
+
+
+# ------------------------------------------------------ library-built factor
+
+def test_library_factor_against_oracle_factor(T, ctx):
+    g, m, beta, tol = 32, 64, 0.1, 1e-5
+    xy = synth.grid_xy(g)
+    n = g * g
+    F = T.Factor.build(ctx, {"xy": xy, "beta": beta}, n, m, tol)
+    perm, diag, ranks, U, V = F.export()
+    assert np.array_equal(perm, OF.morton_order(xy))
+    Lref = np.linalg.cholesky(OF.exp_cov(xy, beta, perm))
+    ref = OF.tlr_from_dense(Lref, m, tol)
+    for i in range(n // m):
+        assert np.allclose(np.tril(diag[i]), Lref[i * m:(i + 1) * m, i * m:(i + 1) * m], atol=1e-12)
+        for j in range(i):
+            T_ = Lref[i * m:(i + 1) * m, j * m:(j + 1) * m]
+            assert np.linalg.norm(T_ - U[(i, j)] @ V[(i, j)].T, 2) <= tol * 1.01 + 1e-12
+            assert abs(int(ranks[i, j]) - int(ref[1][i, j])) <= 1
+    # the estimate on the library's factor, against the oracle on the same factor
+    b = synth.upper_limits_uniform(n, 17)
+    a = np.full(n, -np.inf)
+    res = T.probability(ctx, F, a, b, 500, 4, 5, return_logp=True)
+    ref_res, ref_logp = oracle.probability((diag, ranks, U, V), a[perm], b[perm], 0.0, 500, 4, 5)
+    assert_logp_close(res["logp"], ref_logp)
+    assert_estimate_close(res, ref_res)
