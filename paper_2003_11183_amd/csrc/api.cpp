@@ -53,31 +53,51 @@ struct Scratch {
   }
 };
 
-// HIP events around launches, summed per kernel kind.
+// Samples per call from which the chunks run on worker streams, the number
+// of worker streams, and the device memory the chunk buffers may take.
+constexpr int64_t kMultiStreamSamples = 131072;
+constexpr int kWorkerStreams = 2;
+constexpr int64_t kScratchBudget = int64_t{64} << 30;
+
+// Events created during one call, destroyed on scope exit.
+struct Events {
+  std::vector<hipEvent_t> evs;
+  ~Events() {
+    for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+  }
+  hipEvent_t make() {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    evs.push_back(e);
+    return e;
+  }
+};
+
+// HIP events around launches (on the launch's own stream), summed per
+// kernel kind.
 struct Profiler {
   bool on;
-  hipStream_t stream;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
   int open_kind = -1;
   hipEvent_t open_ev = nullptr;
-  Profiler(bool enable, hipStream_t s) : on(enable), stream(s) {}
+  explicit Profiler(bool enable) : on(enable) {}
   ~Profiler() {
     for (auto &m : marks) {
-      hipEventDestroy(m.second.first);
-      hipEventDestroy(m.second.second);
+      (void)hipEventDestroy(m.second.first);
+      (void)hipEventDestroy(m.second.second);
     }
   }
-  void begin(int kind) {
+  void begin(int kind, hipStream_t s) {
     if (!on) return;
-    hipEventCreate(&open_ev);
-    hipEventRecord(open_ev, stream);
+    (void)hipEventCreate(&open_ev);
+    (void)hipEventRecord(open_ev, s);
     open_kind = kind;
   }
-  void end() {
+  void end(hipStream_t s) {
     if (!on) return;
     hipEvent_t e;
-    hipEventCreate(&e);
-    hipEventRecord(e, stream);
+    (void)hipEventCreate(&e);
+    (void)hipEventRecord(e, s);
     marks.push_back({open_kind, {open_ev, e}});
   }
   void collect(tlrqmc_result *r) {
@@ -87,7 +107,7 @@ struct Profiler {
     }
     for (auto &m : marks) {
       float ms = 0.f;
-      hipEventElapsedTime(&ms, m.second.first, m.second.second);
+      (void)hipEventElapsedTime(&ms, m.second.first, m.second.second);
       r->kernel_seconds[m.first] += ms * 1e-3;
       r->kernel_launches[m.first] += 1;
     }
@@ -101,6 +121,15 @@ bool check_launch(const char *what) {
     return false;
   }
   return true;
+}
+
+// After a failed launch or copy: drain the streams, keep the first message.
+int fail_device(tlrqmc_ctx *ctx, size_t nworkers) {
+  const hipError_t e = hipGetLastError();
+  (void)hipStreamSynchronize(ctx->stream);
+  for (size_t w = 0; w < nworkers && w < ctx->workers.size(); ++w) (void)hipStreamSynchronize(ctx->workers[w]);
+  if (tlrqmc_last_error()[0] == '\0') fail(TLRQMC_EDEVICE, "HIP error: %s", hipGetErrorString(e));
+  return TLRQMC_EDEVICE;
 }
 
 void finish_estimate(const std::vector<double> &part, int M, int64_t N, tlrqmc_result *out) {
@@ -183,13 +212,16 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
     }
     return TLRQMC_OK;
   }
-  // chunking: Z (k_tot rows) + Y + Delta (padded tile rows) per sample
+  // Chunking: each sample needs Z (k_tot rows), Y and Delta (padded tile
+  // rows).  Large runs are split over two worker streams so that their
+  // launches overlap (see tlrqmc_ctx::workers).
   const int64_t mpad = round_up(f->m, 64);
   const int64_t per_sample = 8 * (f->k_tot + 2 * mpad + 2);
+  const int nstream = count >= kMultiStreamSamples ? kWorkerStreams : 1;
   int64_t chunk = opts->chunk_samples;
   if (chunk <= 0) {
-    const int64_t budget = int64_t{40} << 30;
-    chunk = std::max<int64_t>(256, budget / per_sample);
+    const int64_t budget = kScratchBudget / nstream;
+    chunk = std::max<int64_t>(256, std::min<int64_t>(budget / per_sample, (count + nstream - 1) / nstream));
   }
   chunk = round_up(std::min(chunk, count), 256);
   const int64_t ld = chunk;
@@ -198,14 +230,25 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
   double *d_b = sc.get<double>(n);
   uint64_t *d_D = sc.get<uint64_t>(static_cast<size_t>(M) * (n + 1));
   double *d_logp = sc.get<double>(count);
-  double *d_R = nu > 0 ? sc.get<double>(chunk) : nullptr;
-  double *d_Y = sc.get<double>(static_cast<size_t>(mpad) * ld);
-  double *d_Dl = r > 1 ? sc.get<double>(static_cast<size_t>(mpad) * ld) : nullptr;
-  double *d_Z = f->k_tot > 0 ? sc.get<double>(static_cast<size_t>(f->k_tot) * ld) : nullptr;
   double *d_part = reduce ? sc.get<double>(3 * M) : nullptr;
-  if (!d_b || !d_D || !d_logp || !d_Y || (two_sided && !d_a) || (nu > 0 && !d_R) ||
-      (r > 1 && !d_Dl) || (f->k_tot > 0 && !d_Z) || (reduce && !d_part))
-    return fail(TLRQMC_ENOMEM, "device allocation failed (chunk of %lld samples)", static_cast<long long>(chunk));
+  if (!d_b || !d_D || !d_logp || (two_sided && !d_a) || (reduce && !d_part))
+    return fail(TLRQMC_ENOMEM, "device allocation failed");
+  struct Lane {
+    hipStream_t s;
+    double *Y, *Dl, *Z, *R;
+  };
+  std::vector<Lane> lanes(nstream);
+  if (nstream > 1 && ctx->worker_streams(nstream) != TLRQMC_OK) return TLRQMC_EDEVICE;
+  for (int w = 0; w < nstream; ++w) {
+    Lane &L = lanes[w];
+    L.s = nstream > 1 ? ctx->workers[w] : ctx->stream;
+    L.Y = sc.get<double>(static_cast<size_t>(mpad) * ld);
+    L.Dl = r > 1 ? sc.get<double>(static_cast<size_t>(mpad) * ld) : nullptr;
+    L.Z = f->k_tot > 0 ? sc.get<double>(static_cast<size_t>(f->k_tot) * ld) : nullptr;
+    L.R = nu > 0 ? sc.get<double>(chunk) : nullptr;
+    if (!L.Y || (r > 1 && !L.Dl) || (f->k_tot > 0 && !L.Z) || (nu > 0 && !L.R))
+      return fail(TLRQMC_ENOMEM, "device allocation failed (chunk of %lld samples)", static_cast<long long>(chunk));
+  }
   const std::vector<uint64_t> shifts = splitmix64_table(opts->seed, static_cast<int64_t>(M) * (n + 1));
   hipStream_t st = ctx->stream;
   if (two_sided && hipMemcpyAsync(d_a, ap.data(), n * 8, hipMemcpyHostToDevice, st) != hipSuccess)
@@ -213,66 +256,85 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
   if (hipMemcpyAsync(d_b, bp.data(), n * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(d_D, shifts.data(), shifts.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess)
     return fail(TLRQMC_EDEVICE, "copy of limits or shifts failed");
-  hipEvent_t ev0, ev1;
-  hipEventCreate(&ev0);
-  hipEventCreate(&ev1);
-  Profiler prof(opts->profile != 0, st);
-  hipEventRecord(ev0, st);
+  Events evs;
+  hipEvent_t ev0 = evs.make(), ev1 = evs.make(), ev_in = evs.make();
+  if (!ev0 || !ev1 || !ev_in) return fail(TLRQMC_EDEVICE, "hipEventCreate failed");
+  Profiler prof(opts->profile != 0);
+  (void)hipEventRecord(ev0, st);
+  (void)hipEventRecord(ev_in, st);
+  if (nstream > 1)
+    for (auto &L : lanes) (void)hipStreamWaitEvent(L.s, ev_in, 0);
   int chunks = 0;
-  for (int64_t c0 = 0; c0 < count; c0 += chunk) {
-    const int64_t cnt = std::min(chunk, count - c0);
-    ++chunks;
-    InitParams ip{g0 + c0, cnt, N, f->d_gen, d_D, n + 1, nu, d_logp + c0, d_R};
-    prof.begin(TLRQMC_KERNEL_INIT);
-    launch_init(st, ip);
-    prof.end();
-    if (!check_launch("init")) goto fail_dev;
+  for (int64_t base = 0; base < count; base += chunk * nstream) {
+    // one round: up to nstream chunks, enqueued tile by tile across streams
+    std::vector<std::pair<int64_t, int64_t>> cs;
+    for (int w = 0; w < nstream; ++w) {
+      const int64_t c0 = base + w * chunk;
+      if (c0 < count) cs.push_back({c0, std::min(chunk, count - c0)});
+    }
+    chunks += static_cast<int>(cs.size());
+    for (size_t w = 0; w < cs.size(); ++w) {
+      const Lane &L = lanes[w];
+      InitParams ip{g0 + cs[w].first, cs[w].second, N, f->d_gen, d_D, n + 1, nu, d_logp + cs[w].first, L.R};
+      prof.begin(TLRQMC_KERNEL_INIT, L.s);
+      launch_init(L.s, ip);
+      prof.end(L.s);
+      if (!check_launch("init")) return fail_device(ctx, lanes.size());
+    }
     for (int j = 0; j < r; ++j) {
-      if (j > 0 && f->krow[j] > 0) {
-        LrParams lp{cnt, ld, f->tm[j], static_cast<int>(f->krow[j]), f->urow_ld[j],
-                    f->d_urow + f->urow_off[j], d_Z + f->zoff[j] * ld, d_Dl, nullptr};
-        prof.begin(TLRQMC_KERNEL_DELTA);
-        launch_delta_f64(st, lp);
-        prof.end();
-        if (!check_launch("delta")) goto fail_dev;
-      }
-      SweepParams sp{g0 + c0, cnt, N, ld, n + 1, f->tm[j], static_cast<int>(1 + f->toff[j]),
-                     f->d_diag + f->diag_off[j], two_sided ? d_a + f->toff[j] : nullptr,
-                     d_b + f->toff[j], (j > 0 && f->krow[j] > 0) ? d_Dl : nullptr, d_R,
-                     f->d_gen, d_D, d_logp + c0, d_Y};
-      prof.begin(TLRQMC_KERNEL_SWEEP);
-      launch_sweep(st, sp, two_sided, nu > 0);
-      prof.end();
-      if (!check_launch("sweep")) goto fail_dev;
-      if (j < r - 1 && f->kcol[j] > 0) {
-        LrParams lp{cnt, ld, static_cast<int>(f->kcol[j]), f->tm[j], f->vpan_ld[j],
-                    f->d_vpan + f->vpan_off[j], d_Y, d_Z, f->d_zmap + f->zmap_off[j]};
-        prof.begin(TLRQMC_KERNEL_ZPROJ);
-        launch_zproj_f64(st, lp);
-        prof.end();
-        if (!check_launch("zproj")) goto fail_dev;
+      for (size_t w = 0; w < cs.size(); ++w) {
+        const Lane &L = lanes[w];
+        const int64_t c0 = cs[w].first, cnt = cs[w].second;
+        if (j > 0 && f->krow[j] > 0) {
+          LrParams lp{cnt, ld, f->tm[j], static_cast<int>(f->krow[j]), f->urow_ld[j],
+                      f->d_urow + f->urow_off[j], L.Z + f->zoff[j] * ld, L.Dl, nullptr};
+          prof.begin(TLRQMC_KERNEL_DELTA, L.s);
+          launch_delta_f64(L.s, lp);
+          prof.end(L.s);
+          if (!check_launch("delta")) return fail_device(ctx, lanes.size());
+        }
+        SweepParams sp{g0 + c0, cnt, N, ld, n + 1, f->tm[j], static_cast<int>(1 + f->toff[j]),
+                       f->d_diag + f->diag_off[j], two_sided ? d_a + f->toff[j] : nullptr,
+                       d_b + f->toff[j], (j > 0 && f->krow[j] > 0) ? L.Dl : nullptr, L.R,
+                       f->d_gen, d_D, d_logp + c0, L.Y};
+        prof.begin(TLRQMC_KERNEL_SWEEP, L.s);
+        launch_sweep(L.s, sp, two_sided, nu > 0);
+        prof.end(L.s);
+        if (!check_launch("sweep")) return fail_device(ctx, lanes.size());
+        if (j < r - 1 && f->kcol[j] > 0) {
+          LrParams lp{cnt, ld, static_cast<int>(f->kcol[j]), f->tm[j], f->vpan_ld[j],
+                      f->d_vpan + f->vpan_off[j], L.Y, L.Z, f->d_zmap + f->zmap_off[j]};
+          prof.begin(TLRQMC_KERNEL_ZPROJ, L.s);
+          launch_zproj_f64(L.s, lp);
+          prof.end(L.s);
+          if (!check_launch("zproj")) return fail_device(ctx, lanes.size());
+        }
       }
     }
   }
+  if (nstream > 1)
+    for (auto &L : lanes) {
+      hipEvent_t e = evs.make();
+      (void)hipEventRecord(e, L.s);
+      (void)hipStreamWaitEvent(st, e, 0);
+    }
   if (reduce) {
     ReduceParams rp{N, d_logp, d_part};
-    prof.begin(TLRQMC_KERNEL_REDUCE);
+    prof.begin(TLRQMC_KERNEL_REDUCE, st);
     launch_reduce(st, rp, M);
-    prof.end();
-    if (!check_launch("reduce")) goto fail_dev;
+    prof.end(st);
+    if (!check_launch("reduce")) return fail_device(ctx, lanes.size());
   }
-  hipEventRecord(ev1, st);
+  (void)hipEventRecord(ev1, st);
   {
     std::vector<double> part(reduce ? 3 * M : 0);
     if (reduce && hipMemcpyAsync(part.data(), d_part, part.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess)
-      goto fail_dev;
+      return fail_device(ctx, lanes.size());
     if (logp_host && hipMemcpyAsync(logp_host, d_logp, count * 8, hipMemcpyDeviceToHost, st) != hipSuccess)
-      goto fail_dev;
-    if (hipStreamSynchronize(st) != hipSuccess) goto fail_dev;
+      return fail_device(ctx, lanes.size());
+    if (hipStreamSynchronize(st) != hipSuccess) return fail_device(ctx, lanes.size());
     float ms = 0.f;
-    hipEventElapsedTime(&ms, ev0, ev1);
-    hipEventDestroy(ev0);
-    hipEventDestroy(ev1);
+    (void)hipEventElapsedTime(&ms, ev0, ev1);
     if (out) {
       if (reduce) finish_estimate(part, M, N, out);
       out->seconds = ms * 1e-3;
@@ -281,12 +343,6 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
     }
   }
   return TLRQMC_OK;
-fail_dev:
-  hipStreamSynchronize(st);
-  hipEventDestroy(ev0);
-  hipEventDestroy(ev1);
-  if (tlrqmc_last_error()[0] == '\0') fail(TLRQMC_EDEVICE, "HIP error: %s", hipGetErrorString(hipGetLastError()));
-  return TLRQMC_EDEVICE;
 }
 
 }  // namespace
@@ -299,6 +355,16 @@ void *tlrqmc_ctx::dmalloc(size_t bytes) {
   void *p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
   return p;
+}
+
+int tlrqmc_ctx::worker_streams(int count) {
+  while (static_cast<int>(workers.size()) < count) {
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+      return fail(TLRQMC_EDEVICE, "hipStreamCreateWithFlags failed");
+    workers.push_back(s);
+  }
+  return TLRQMC_OK;
 }
 
 void tlrqmc_ctx::dfree(void *p) {
@@ -331,7 +397,15 @@ int tlrqmc_ctx_create(int device, void *hip_stream, const tlrqmc_allocator *allo
   return TLRQMC_OK;
 }
 
-void tlrqmc_ctx_destroy(tlrqmc_ctx *ctx) { delete ctx; }
+void tlrqmc_ctx_destroy(tlrqmc_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  for (hipStream_t s : ctx->workers) {
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+  }
+  delete ctx;
+}
 
 int tlrqmc_factor_import(tlrqmc_ctx *ctx, int64_t n, int m, const int32_t *perm, const double *diag,
                          const int32_t *ranks, const double *U, const double *V, tlrqmc_factor **out) {

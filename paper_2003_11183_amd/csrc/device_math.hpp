@@ -50,12 +50,32 @@ constexpr double kLogSqrt2Pi = 0.91893853320467274178;
 constexpr double kInvSqrtPi = 0.56418958354775628695;
 constexpr double kLog4 = 1.38629436111989061883;
 
+// a * b + c with the wave-uniform c read straight from its scalar registers
+// (v_fma_f64 takes one scalar operand).  Left to itself the compiler ties
+// the accumulator to c and copies c into vector registers first, tripling
+// the instruction count of every polynomial step.
+__device__ __forceinline__ double fma_s(double a, double b, double c) {
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+  return r;
+}
+
 template <int OFF, int N>
 __device__ __forceinline__ double horner(ctab_t T, double s) {
-  double acc = T[OFF + N - 1];
+  double acc = fma_s(T[OFF + N - 1], s, T[OFF + N - 2]);
 #pragma unroll
-  for (int i = N - 2; i >= 0; --i) acc = fma(acc, s, T[OFF + i]);
+  for (int i = N - 3; i >= 0; --i) acc = fma_s(acc, s, T[OFF + i]);
   return acc;
+}
+
+// a / d for d in a range far from overflow and underflow: hardware
+// reciprocal, two Newton steps and one residual correction.
+__device__ __forceinline__ double div_safe(double a, double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(fma(-d, r, 1.0), r, r);
+  r = fma(fma(-d, r, 1.0), r, r);
+  const double q = a * r;
+  return fma(fma(-d, q, a), r, q);
 }
 
 constexpr double kLn2Hi = 6.93147180559945286227e-01;
@@ -81,7 +101,7 @@ __device__ __forceinline__ double log_pos(ctab_t T, double x) {
     e -= 1;
   }
   const double f = m - 1.0;
-  const double s = f / (2.0 + f);
+  const double s = div_safe(f, 2.0 + f);
   const double v = s * s;
   const double lm = fma(s * v, horner<kOffLog, kNLog>(T, (v - kLogC) * kLogH), 2.0 * s);
   const double de = static_cast<double>(e);
@@ -94,14 +114,10 @@ __device__ __forceinline__ double log1p_t(ctab_t T, double x) {
   return log_pos(T, u) + (x - (u - 1.0)) / u;
 }
 
-// erfcx(z) for z >= 0 (z = +inf gives 0).
-__device__ inline double erfcx_pos(ctab_t T, double z) {
-  if (z <= kErfcxZmax) {
-    const double t = (z - kErfcxK) / (z + kErfcxK);
-    const double g = horner<kOffErfcx, kNErfcx>(T, (t - kErfcxC) * kErfcxH);
-    return g * (1.0 - t) * 0.5;
-  }
-  // sum_k (-1)^k (2k-1)!! / (2 z^2)^k, divided by z sqrt(pi)
+// erfcx(z) for z > 12 (z = +inf gives 0): the asymptotic series
+// sum_k (-1)^k (2k-1)!! / (2 z^2)^k divided by z sqrt(pi).  Out of line: it
+// is reached only below Phi(-17).
+__device__ __forceinline__ double erfcx_large(double z) {
   const double v = 0.5 / (z * z);
   double acc = 0.0, coef = 1.0;
   double pw = 1.0;
@@ -112,6 +128,16 @@ __device__ inline double erfcx_pos(ctab_t T, double z) {
     coef *= -(2.0 * k + 1.0);
   }
   return acc * kInvSqrtPi / z;
+}
+
+// erfcx(z) for z >= 0.
+__device__ __forceinline__ double erfcx_pos(ctab_t T, double z) {
+  if (z <= kErfcxZmax) {
+    const double t = div_safe(z - kErfcxK, z + kErfcxK);
+    const double g = horner<kOffErfcx, kNErfcx>(T, (t - kErfcxC) * kErfcxH);
+    return g * (1.0 - t) * 0.5;
+  }
+  return erfcx_large(z);
 }
 
 // q = Phi(-|x|) and lq = log q, for finite x.
@@ -139,14 +165,21 @@ __device__ inline double log_Phi(ctab_t T, double x) {
   return x < 0.0 ? lq : log1p_t(T, -q);
 }
 
-// p(w) of Phi^-1 on the five intervals (s = sqrt(w) beyond the first).
-__device__ inline double inv_poly(ctab_t T, double wv) {
-  if (wv < 6.25) return horner<kOffInv1, kNInv1>(T, (wv - kInvC1) * kInvH1);
+// p(w) of Phi^-1 for w >= 6.25 (u outside [5e-4, 1 - 5e-4]), in sqrt(w)
+// on four intervals.  Out of line: rare, and it would otherwise add its
+// registers to the main path.
+__device__ __forceinline__ double inv_poly_tail(ctab_t T, double wv) {
   const double s = sqrt(wv);
   if (s < 4.0) return horner<kOffInv2, kNInv2>(T, (s - kInvC2) * kInvH2);
   if (s < 8.0) return horner<kOffInv3, kNInv3>(T, (s - kInvC3) * kInvH3);
   if (s < 14.0) return horner<kOffInv4, kNInv4>(T, (s - kInvC4) * kInvH4);
   return horner<kOffInv5, kNInv5>(T, (s - kInvC5) * kInvH5);
+}
+
+// p(w) of Phi^-1: a polynomial in w on [0, 6.25], the tail beyond.
+__device__ __forceinline__ double inv_poly(ctab_t T, double wv) {
+  if (wv < 6.25) return horner<kOffInv1, kNInv1>(T, (wv - kInvC1) * kInvH1);
+  return inv_poly_tail(T, wv);
 }
 
 __device__ inline double Phi_inv(ctab_t T, double u) {

@@ -30,8 +30,13 @@ struct tlrqmc_ctx {
   hipStream_t stream = nullptr;
   tlrqmc_allocator alloc{};
   bool has_alloc = false;
+  // Worker streams (default priority) on which independent sample chunks
+  // run concurrently, so that the last partial round of waves of one
+  // chunk's launch is filled by another chunk's work.
+  std::vector<hipStream_t> workers;
   void *dmalloc(size_t bytes);
   void dfree(void *p);
+  int worker_streams(int count);
 };
 
 // Device-resident TLR factor.  Host vectors keep the exchange layout for

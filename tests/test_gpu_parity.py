@@ -234,3 +234,16 @@ def test_library_factor_against_oracle_factor(T, ctx):
     ref_res, ref_logp = oracle.probability((diag, ranks, U, V), a[perm], b[perm], 0.0, 500, 4, 5)
     assert_logp_close(res["logp"], ref_logp)
     assert_estimate_close(res, ref_res)
+
+
+@pytest.mark.parametrize("chunk", [0, 20480])
+def test_worker_streams_and_rounds(T, ctx, chunk):
+    """200,000 samples: chunks on two worker streams (several rounds when small)."""
+    n, m, N, M = 200, 64, 50_000, 4
+    fac = synth.random_tlr_factor(n, m, seed=44, rank_mean=3.0)
+    b = np.linspace(0.3, 2.8, n)
+    a = np.full(n, -np.inf)
+    res, ref, lg, lr = run_both(T, ctx, fac, np.arange(n, dtype=np.int32), a, b, 5.0, N, M, 21, chunk=chunk)
+    assert res["chunks"] == (2 if chunk == 0 else 10)
+    assert_logp_close(lg, lr)
+    assert_estimate_close(res, ref)
