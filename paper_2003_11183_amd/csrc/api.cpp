@@ -181,7 +181,6 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
   if (N < 1) return fail(TLRQMC_EINVAL, "n_samples must be >= 1");
   if (M < 2 || M > 64) return fail(TLRQMC_EINVAL, "n_shifts must be in [2, 64]");
   if (opts->precision != 0 && opts->precision != 1) return fail(TLRQMC_EINVAL, "precision must be 0 or 1");
-  if (opts->precision == 1) return fail(TLRQMC_EINVAL, "precision form 1 is not available in this build");
   if (!(nu >= 0.0) || std::isinf(nu)) return fail(TLRQMC_EINVAL, "nu must be finite and > 0 (0 selects MVN)");
   if (N > (int64_t{1} << 40) / M) return fail(TLRQMC_EINVAL, "too many samples");
   const int64_t n = f->n;
@@ -215,8 +214,9 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
   // Chunking: each sample needs Z (k_tot rows), Y and Delta (padded tile
   // rows).  Large runs are split over two worker streams so that their
   // launches overlap (see tlrqmc_ctx::workers).
+  const bool prec = opts->precision == 1;
   const int64_t mpad = round_up(f->m, 64);
-  const int64_t per_sample = 8 * (f->k_tot + 2 * mpad + 2);
+  const int64_t per_sample = prec ? 4 * f->zp_tot + 12 * mpad + 16 : 8 * (f->k_tot + 2 * mpad + 2);
   const int nstream = count >= kMultiStreamSamples ? kWorkerStreams : 1;
   int64_t chunk = opts->chunk_samples;
   if (chunk <= 0) {
@@ -236,6 +236,7 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
   struct Lane {
     hipStream_t s;
     double *Y, *Dl, *Z, *R;
+    float *DlF, *ZF;
   };
   std::vector<Lane> lanes(nstream);
   if (nstream > 1 && ctx->worker_streams(nstream) != TLRQMC_OK) return TLRQMC_EDEVICE;
@@ -243,10 +244,13 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
     Lane &L = lanes[w];
     L.s = nstream > 1 ? ctx->workers[w] : ctx->stream;
     L.Y = sc.get<double>(static_cast<size_t>(mpad) * ld);
-    L.Dl = r > 1 ? sc.get<double>(static_cast<size_t>(mpad) * ld) : nullptr;
-    L.Z = f->k_tot > 0 ? sc.get<double>(static_cast<size_t>(f->k_tot) * ld) : nullptr;
+    L.Dl = (!prec && r > 1) ? sc.get<double>(static_cast<size_t>(mpad) * ld) : nullptr;
+    L.Z = (!prec && f->k_tot > 0) ? sc.get<double>(static_cast<size_t>(f->k_tot) * ld) : nullptr;
+    L.DlF = (prec && r > 1) ? sc.get<float>(static_cast<size_t>(mpad) * ld) : nullptr;
+    L.ZF = (prec && f->k_tot > 0) ? sc.get<float>(static_cast<size_t>(f->zp_tot) * ld) : nullptr;
     L.R = nu > 0 ? sc.get<double>(chunk) : nullptr;
-    if (!L.Y || (r > 1 && !L.Dl) || (f->k_tot > 0 && !L.Z) || (nu > 0 && !L.R))
+    if (!L.Y || (!prec && r > 1 && !L.Dl) || (!prec && f->k_tot > 0 && !L.Z) || (prec && r > 1 && !L.DlF) ||
+        (prec && f->k_tot > 0 && !L.ZF) || (nu > 0 && !L.R))
       return fail(TLRQMC_ENOMEM, "device allocation failed (chunk of %lld samples)", static_cast<long long>(chunk));
   }
   const std::vector<uint64_t> shifts = splitmix64_table(opts->seed, static_cast<int64_t>(M) * (n + 1));
@@ -285,27 +289,42 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
       for (size_t w = 0; w < cs.size(); ++w) {
         const Lane &L = lanes[w];
         const int64_t c0 = cs[w].first, cnt = cs[w].second;
-        if (j > 0 && f->krow[j] > 0) {
-          LrParams lp{cnt, ld, f->tm[j], static_cast<int>(f->krow[j]), f->urow_ld[j],
-                      f->d_urow + f->urow_off[j], L.Z + f->zoff[j] * ld, L.Dl, nullptr};
+        const bool has_delta = j > 0 && f->krow[j] > 0;
+        if (has_delta) {
           prof.begin(TLRQMC_KERNEL_DELTA, L.s);
-          launch_delta_f64(L.s, lp);
+          if (prec) {
+            const unsigned short *u = f->d_ubf + f->ubf_off[j];
+            MfmaDeltaParams mp{cnt, ld, f->tm[j], static_cast<int>(f->krow[j]), f->kp_row[j], u,
+                               u + f->ubf_size[j], L.ZF + f->zoffp[j] * ld, L.DlF};
+            launch_delta_mfma(L.s, mp);
+          } else {
+            LrParams lp{cnt, ld, f->tm[j], static_cast<int>(f->krow[j]), f->urow_ld[j],
+                        f->d_urow + f->urow_off[j], L.Z + f->zoff[j] * ld, L.Dl, nullptr};
+            launch_delta_f64(L.s, lp);
+          }
           prof.end(L.s);
           if (!check_launch("delta")) return fail_device(ctx, lanes.size());
         }
         SweepParams sp{g0 + c0, cnt, N, ld, n + 1, f->tm[j], static_cast<int>(1 + f->toff[j]),
                        f->d_diag + f->diag_off[j], two_sided ? d_a + f->toff[j] : nullptr,
-                       d_b + f->toff[j], (j > 0 && f->krow[j] > 0) ? L.Dl : nullptr, L.R,
-                       f->d_gen, d_D, d_logp + c0, L.Y};
+                       d_b + f->toff[j], (has_delta && !prec) ? L.Dl : nullptr,
+                       (has_delta && prec) ? L.DlF : nullptr, L.R, f->d_gen, d_D, d_logp + c0, L.Y};
         prof.begin(TLRQMC_KERNEL_SWEEP, L.s);
         launch_sweep(L.s, sp, two_sided, nu > 0);
         prof.end(L.s);
         if (!check_launch("sweep")) return fail_device(ctx, lanes.size());
         if (j < r - 1 && f->kcol[j] > 0) {
-          LrParams lp{cnt, ld, static_cast<int>(f->kcol[j]), f->tm[j], f->vpan_ld[j],
-                      f->d_vpan + f->vpan_off[j], L.Y, L.Z, f->d_zmap + f->zmap_off[j]};
           prof.begin(TLRQMC_KERNEL_ZPROJ, L.s);
-          launch_zproj_f64(L.s, lp);
+          if (prec) {
+            const unsigned short *v = f->d_vbf + f->vbf_off[j];
+            MfmaZprojParams zp{cnt, ld, f->tm[j], f->vbf_mp[j], static_cast<int>(f->kcol[j]), v,
+                               v + f->vbf_size[j], L.Y, f->d_zmapp + f->zmap_off[j], L.ZF};
+            launch_zproj_mfma(L.s, zp);
+          } else {
+            LrParams lp{cnt, ld, static_cast<int>(f->kcol[j]), f->tm[j], f->vpan_ld[j],
+                        f->d_vpan + f->vpan_off[j], L.Y, L.Z, f->d_zmap + f->zmap_off[j]};
+            launch_zproj_f64(L.s, lp);
+          }
           prof.end(L.s);
           if (!check_launch("zproj")) return fail_device(ctx, lanes.size());
         }
@@ -451,6 +470,9 @@ void tlrqmc_factor_free(tlrqmc_factor *f) {
     f->ctx->dfree(f->d_vpan);
     f->ctx->dfree(f->d_zmap);
     f->ctx->dfree(f->d_gen);
+    f->ctx->dfree(f->d_ubf);
+    f->ctx->dfree(f->d_vbf);
+    f->ctx->dfree(f->d_zmapp);
   }
   delete f;
 }

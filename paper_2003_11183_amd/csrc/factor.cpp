@@ -29,6 +29,22 @@ int upload(tlrqmc_ctx *ctx, const void *host, size_t bytes, void **dev, int64_t 
   return TLRQMC_OK;
 }
 
+// x = hi + lo with hi = bf16(float(x)), lo = bf16(float(x - hi)), both
+// rounded to nearest even.
+void split_bf16(double x, unsigned short &hi, unsigned short &lo) {
+  auto bits = [](float v) {
+    uint32_t u;
+    std::memcpy(&u, &v, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return static_cast<unsigned short>(u >> 16);
+  };
+  hi = bits(static_cast<float>(x));
+  const uint32_t hb = static_cast<uint32_t>(hi) << 16;
+  float hf;
+  std::memcpy(&hf, &hb, 4);
+  lo = bits(static_cast<float>(x - static_cast<double>(hf)));
+}
+
 }  // namespace
 
 int factor_build(tlrqmc_ctx *ctx, int64_t n, int m, const int32_t *perm, const double *diag,
@@ -211,6 +227,53 @@ int factor_build(tlrqmc_ctx *ctx, int64_t n, int m, const int32_t *perm, const d
   }
   f->vpan_off[r] = static_cast<int64_t>(hv.size());
   f->zmap_off[r] = static_cast<int64_t>(hz.size());
+  // ---- precision form: BF16 hi/lo splits and the padded Z layout
+  f->kp_row.assign(r, 0);
+  f->zoffp.assign(r + 1, 0);
+  for (int i = 0; i < r; ++i) {
+    f->kp_row[i] = static_cast<int>(round_up(f->krow[i], 32));
+    f->zoffp[i + 1] = f->zoffp[i] + f->kp_row[i];
+  }
+  f->zp_tot = f->zoffp[r];
+  std::vector<unsigned short> hub, hvb;
+  std::vector<int32_t> hzp;
+  f->ubf_off.assign(r + 1, 0);
+  f->ubf_size.assign(r, 0);
+  for (int i = 0; i < r; ++i) {
+    const int rt = delta_mfma_rt(f->tm[i]);
+    const int64_t rows = round_up(f->tm[i], 64 * rt);
+    const int64_t kp = f->kp_row[i];
+    f->ubf_off[i] = static_cast<int64_t>(hub.size());
+    f->ubf_size[i] = rows * kp;
+    hub.resize(hub.size() + 2 * rows * kp, 0);
+    unsigned short *hi = hub.data() + f->ubf_off[i], *lo = hi + rows * kp;
+    const double *src = hu.data() + f->urow_off[i];  // column-major, lda = urow_ld[i]
+    for (int64_t col = 0; col < f->krow[i]; ++col)
+      for (int t = 0; t < f->tm[i]; ++t) split_bf16(src[col * f->urow_ld[i] + t], hi[t * kp + col], lo[t * kp + col]);
+  }
+  f->ubf_off[r] = static_cast<int64_t>(hub.size());
+  f->vbf_off.assign(r + 1, 0);
+  f->vbf_size.assign(r, 0);
+  f->vbf_mp.assign(r, 0);
+  for (int j = 0; j < r; ++j) {
+    const int64_t kp = round_up(f->kcol[j], 32);
+    const int64_t mp = round_up(f->tm[j], 32);
+    f->vbf_mp[j] = static_cast<int>(mp);
+    f->vbf_off[j] = static_cast<int64_t>(hvb.size());
+    f->vbf_size[j] = kp * mp;
+    hvb.resize(hvb.size() + 2 * kp * mp, 0);
+    unsigned short *hi = hvb.data() + f->vbf_off[j], *lo = hi + kp * mp;
+    const double *src = hv.data() + f->vpan_off[j];  // row-major, ldv = vpan_ld[j]
+    for (int64_t col = 0; col < f->kcol[j]; ++col) {
+      for (int t = 0; t < f->tm[j]; ++t) split_bf16(src[static_cast<int64_t>(t) * f->vpan_ld[j] + col], hi[col * mp + t], lo[col * mp + t]);
+      // padded Z row of the same (i, j, c) as the unpadded zmap entry
+      const int32_t zr = hz[f->zmap_off[j] + col];
+      int i = 0;
+      while (f->zoff[i + 1] <= zr) ++i;
+      hzp.push_back(static_cast<int32_t>(f->zoffp[i] + (zr - f->zoff[i])));
+    }
+  }
+  f->vbf_off[r] = static_cast<int64_t>(hvb.size());
   // lattice generators A_0..A_n
   const std::vector<uint64_t> gen = richtmyer_generators(n + 1);
   int64_t total = 0;
@@ -220,6 +283,9 @@ int factor_build(tlrqmc_ctx *ctx, int64_t n, int m, const int32_t *perm, const d
   if ((st = upload(ctx, hv.data(), hv.size() * sizeof(double), reinterpret_cast<void **>(&f->d_vpan), total))) return st;
   if ((st = upload(ctx, hz.data(), hz.size() * sizeof(int32_t), reinterpret_cast<void **>(&f->d_zmap), total))) return st;
   if ((st = upload(ctx, gen.data(), gen.size() * sizeof(uint64_t), reinterpret_cast<void **>(&f->d_gen), total))) return st;
+  if ((st = upload(ctx, hub.data(), hub.size() * 2, reinterpret_cast<void **>(&f->d_ubf), total))) return st;
+  if ((st = upload(ctx, hvb.data(), hvb.size() * 2, reinterpret_cast<void **>(&f->d_vbf), total))) return st;
+  if ((st = upload(ctx, hzp.data(), hzp.size() * 4, reinterpret_cast<void **>(&f->d_zmapp), total))) return st;
   if (hipStreamSynchronize(ctx->stream) != hipSuccess) return fail(TLRQMC_EDEVICE, "stream synchronize failed");
   f->device_bytes = total;
   *out = guard.release();

@@ -69,6 +69,20 @@ struct tlrqmc_factor {
   int32_t *d_zmap = nullptr;    // V_panel(j) column -> Z row
   std::vector<int64_t> zmap_off;
   uint64_t *d_gen = nullptr;    // lattice generators A_0..A_n
+  // Precision form: BF16 hi/lo splits of U_row (row-major, k padded to 32,
+  // rows padded to the MFMA block) and of V_panel^T (row-major, t padded to
+  // 32), and a Z layout whose row blocks are padded to 32.
+  unsigned short *d_ubf = nullptr;
+  std::vector<int64_t> ubf_off;  // hi at off, lo at off + ubf_size[i]
+  std::vector<int64_t> ubf_size;
+  std::vector<int> kp_row;       // round_up(krow, 32)
+  unsigned short *d_vbf = nullptr;
+  std::vector<int64_t> vbf_off;
+  std::vector<int64_t> vbf_size;
+  std::vector<int> vbf_mp;       // round_up(m_j, 32)
+  int32_t *d_zmapp = nullptr;    // V_panel(j) column -> padded Z row
+  std::vector<int64_t> zoffp;    // first padded Z row of tile i
+  int64_t zp_tot = 0;
   int64_t device_bytes = 0;
 };
 
@@ -99,6 +113,7 @@ struct SweepParams {
   const double *B;         // blocked tile
   const double *a, *b;     // limits of the tile rows (a unused when one-sided)
   const double *Delta;     // m x ld low-rank update, or null
+  const float *DeltaF;     // the same in FP32 (precision form), or null
   const double *R;         // per chunk sample, or null
   const uint64_t *A, *D;
   double *logp;            // per chunk sample
@@ -121,6 +136,26 @@ struct ReduceParams {
   double *part;            // per shift: max, sum exp(lp - max), dead count
 };
 
+struct MfmaDeltaParams {
+  int64_t count, ld;
+  int rows, K, KP;         // m_i, krow (valid k), krow padded to 32
+  const unsigned short *Uhi, *Ulo;
+  const float *Z;          // first padded Z row of tile i
+  float *Delta;
+};
+
+struct MfmaZprojParams {
+  int64_t count, ld;
+  int mj, mp, Kc;          // tile rows, rows padded to 32, V_panel columns
+  const unsigned short *Vhi, *Vlo;
+  const double *Y;
+  const int32_t *map;
+  float *Z;
+};
+
+int delta_mfma_rt(int rows);
+void launch_delta_mfma(hipStream_t s, const MfmaDeltaParams &p);
+void launch_zproj_mfma(hipStream_t s, const MfmaZprojParams &p);
 void launch_init(hipStream_t s, const InitParams &p);
 void launch_sweep(hipStream_t s, const SweepParams &p, bool two_sided, bool scaled);
 void launch_delta_f64(hipStream_t s, const LrParams &p);

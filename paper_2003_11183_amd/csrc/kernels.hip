@@ -65,6 +65,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepParams p) {
   const int64_t ld = p.ld;
   double *Y = p.Y + si;
   const double *Dl = p.Delta ? p.Delta + si : nullptr;
+  const float *DlF = p.DeltaF ? p.DeltaF + si : nullptr;
   double lp = p.logp[si];
   const int nb = (p.mj + 31) >> 5;
   auto blk = as_const(p.B);
@@ -86,12 +87,14 @@ __global__ __launch_bounds__(256) void k_sweep(SweepParams p) {
       const int row = q * 32 + t;
       const auto col = blk + t * 32;
       double bt = R * bl[row];
-      if (Dl) bt -= Dl[row * ld];
+      double dlt = 0.0;
+      if (Dl) dlt = Dl[row * ld];
+      if (DlF) dlt = static_cast<double>(DlF[row * ld]);
+      bt -= dlt;
       const double w = lattice_point(k, Ag[row], Ds[row]);
       double y, ldel;
       if (TWO_SIDED) {
-        double at = R * al[row];
-        if (Dl) at -= Dl[row * ld];
+        const double at = R * al[row] - dlt;
         ldel = sov_step((at - acc[0]) * col[0], (bt - acc[0]) * col[0], w, y);
       } else {
         ldel = sov_step_upper((bt - acc[0]) * col[0], w, y);

@@ -114,14 +114,19 @@ def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-def _cov(cov: dict) -> tuple[Cov, list]:
-    """tlrqmc_cov from {'xy', 'beta'[, 'variance', 'nugget']} or {'sigma'}."""
+def _cov(cov: dict, n: int | None = None) -> tuple[Cov, list]:
+    """tlrqmc_cov from {'xy', 'beta'[, 'variance', 'nugget']} or {'sigma'},
+    checked against the dimension n."""
     keep = []
     if "sigma" in cov:
         S = np.asfortranarray(cov["sigma"], dtype=np.float64)
+        if S.ndim != 2 or S.shape[0] != S.shape[1] or (n is not None and S.shape[0] != n):
+            raise ValueError(f"sigma must be {n} x {n}, got {S.shape}")
         keep.append(S)
         return Cov(0, 0, S.ctypes.data, S.shape[0], None, 0.0, 0.0, 0.0), keep
     xy = _f64(cov["xy"])
+    if xy.ndim != 2 or xy.shape[1] != 2 or (n is not None and xy.shape[0] != n):
+        raise ValueError(f"xy must be {n} x 2, got {xy.shape}")
     keep.append(xy)
     return Cov(1, 0, None, 0, xy.ctypes.data, float(cov["beta"]), float(cov.get("variance", 1.0)),
                float(cov.get("nugget", 0.0))), keep
@@ -178,7 +183,9 @@ def geometric_order(xy) -> np.ndarray:
 def block_reorder(cov: dict, a, b, m: int, ctx: Context | None = None) -> np.ndarray:
     a, b = _f64(a), _f64(b)
     n = len(a)
-    cv, keep = _cov(cov)
+    if len(b) != n:
+        raise ValueError("a and b must have the same length")
+    cv, keep = _cov(cov, n)
     out = np.empty(n, dtype=np.int32)
     _check(lib().block_reorder(ctx.handle if ctx else None, n, C.byref(cv), a.ctypes.data, b.ctypes.data,
                                int(m), out.ctypes.data))
@@ -219,8 +226,10 @@ class Factor:
     @classmethod
     def build(cls, ctx: Context, cov: dict, n: int, m: int, tol: float, max_rank: int = 0,
               perm=None) -> "Factor":
-        cv, keep = _cov(cov)
+        cv, keep = _cov(cov, n)
         p = None if perm is None else np.ascontiguousarray(perm, dtype=np.int32)
+        if p is not None and p.shape != (n,):
+            raise ValueError("perm must have n entries")
         h = C.c_void_p()
         st = _check(lib().tlr_factor(ctx.handle, n, C.byref(cv), _ptr(p), int(m), float(tol), int(max_rank),
                                      C.byref(h)))
@@ -292,6 +301,9 @@ def probability(ctx: Context, factor: Factor, a, b, N: int, M: int, seed: int, n
     """mvn_prob (nu = 0) or mvt_prob (nu > 0); returns the result dict
     (with 'logp', M x N, when return_logp)."""
     a, b = _f64(a), _f64(b)
+    n = factor.stats()["n"]
+    if a.shape != (n,) or b.shape != (n,):
+        raise ValueError(f"a and b must have {n} entries")
     logp = np.empty(int(N) * int(M)) if return_logp else None
     o = _opts(N, M, seed, precision, logp, profile, chunk)
     res = Result()
@@ -320,6 +332,9 @@ def mvt_prob(ctx, factor, a, b, nu, N, M, seed, **kw):
 def sample_logp(ctx: Context, factor: Factor, a, b, nu: float, N: int, M: int, seed: int, shift: int,
                 k0: int, count: int, precision: int = 0, chunk: int = 0) -> np.ndarray:
     a, b = _f64(a), _f64(b)
+    n = factor.stats()["n"]
+    if a.shape != (n,) or b.shape != (n,):
+        raise ValueError(f"a and b must have {n} entries")
     out = np.empty(int(count))
     o = _opts(N, M, seed, precision, None, False, chunk)
     _check(lib().tlrqmc_sample_logp(ctx.handle, factor.handle, a.ctypes.data, b.ctypes.data, float(nu),

@@ -247,3 +247,47 @@ def test_worker_streams_and_rounds(T, ctx, chunk):
     assert res["chunks"] == (2 if chunk == 0 else 10)
     assert_logp_close(lg, lr)
     assert_estimate_close(res, ref)
+
+
+# ------------------------------------------------------------ precision form
+
+@pytest.mark.parametrize("case", ["exp1024", "ragged-two-sided-mvt"])
+def test_precision_form_within_standard_error(T, ctx, case):
+    """BF16x3 low-rank updates: the estimate stays within the QMC standard
+    error of the oracle's on identical points, and every sample's log P is
+    within 1e-3 max(1, |log P|) of the oracle's."""
+    if case == "exp1024":
+        fac, perm, _ = exp_factor(32, 0.1, 128, 1e-5)
+        n, m, nu = 1024, 128, 0.0
+        b = synth.upper_limits_uniform(n, 2005)
+        a = np.full(n, -np.inf)
+    else:
+        n, m, nu = 1000, 64, 7.0
+        fac = synth.random_tlr_factor(n, m, seed=31, rank_mean=5.0, rank_max=20)
+        perm = np.arange(n, dtype=np.int32)
+        rng = np.random.default_rng(4)
+        b = rng.uniform(0.0, 3.0, n)
+        a = np.where(rng.random(n) < 0.5, -np.inf, b - rng.uniform(0.5, 4.0, n))
+    N, M, seed = 2000, 8, 3
+    F = T.Factor.from_tiles(ctx, n, m, fac[0], fac[1], fac[2], fac[3], perm)
+    res = T.probability(ctx, F, a, b, N, M, seed, nu=nu, precision=1, return_logp=True)
+    ref, ref_logp = oracle.probability(fac, np.asarray(a)[perm], np.asarray(b)[perm], nu, N, M, seed)
+    assert abs(res["p"] - ref["p"]) <= ref["std_err"]
+    err = np.abs(res["logp"] - ref_logp) / np.maximum(1.0, np.abs(ref_logp))
+    print(f"{case}: max per-sample scaled error {err.max():.2e}, "
+          f"|dP|/SE = {abs(res['p'] - ref['p']) / ref['std_err']:.2e}")
+    assert err.max() <= 1e-3
+
+
+def test_precision_form_matches_fp64_form(T, ctx):
+    """Same factor and points in both forms: the difference of the estimates
+    is far inside the standard error."""
+    n, m = 2048, 128
+    xy = synth.grid_xy(46)[:n]
+    F = T.Factor.build(ctx, {"xy": xy, "beta": 0.2}, n, m, 1e-5)
+    b = synth.upper_limits_uniform(n, 77)
+    a = np.full(n, -np.inf)
+    r64 = T.probability(ctx, F, a, b, 20_000, 10, 5, nu=7.0, precision=0)
+    r16 = T.probability(ctx, F, a, b, 20_000, 10, 5, nu=7.0, precision=1)
+    print(f"fp64 {r64['log_p']:.10f} prec {r16['log_p']:.10f} se/p {r64['rel_err']:.3e}")
+    assert abs(r16["p"] - r64["p"]) <= 0.1 * r64["std_err"]
