@@ -1,23 +1,24 @@
 """Benchmark: QMC sample-dimensions per second of the TLR estimator on one GPU.
 
-Workload (default): the Student-t problem at n = 16,384 -- 128 x 128 regular
-grid on the unit square, exponential covariance with range 0.3, nu = 7,
-tile m = 256, off-diagonal tiles truncated at 1e-5, a = -inf, b ~ U(0, 4),
-N = 40,000 lattice points x 10 random shifts.  One step is one full
-estimate (mvt_prob): lattice, chi radii, low-rank limit updates, diagonal
-tile sweeps and the per-shift reductions; the factor is built once before
-timing (the paper also times the integration only).  Inputs are synthetic
-and seeded; the factor and limits are resident on the device when the
-timed region starts.
+Default workload: the Student-t problem at n = 16,384.
 
-Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+- 128 x 128 regular grid on the unit square, exponential covariance with range 0.3, nu = 7.
+- Tile m = 256, off-diagonal tiles truncated at 1e-5, a = -inf, b ~ U(0, 4).
+- N = 40,000 lattice points x 10 random shifts.
+
+One step is one full estimate (mvt_prob): lattice, chi radii, low-rank limit updates, diagonal-tile sweeps and
+the per-shift reductions. It runs in the workload's precision form (BF16x3 MFMA low-rank updates, FP64
+elsewhere); the plain FP64 form is timed on the same problem and reported beside it. The factor is built once
+before timing, since the paper also times the integration only.
+
+Inputs are synthetic and seeded. The factor, limits and shifts are on the device when the timed region starts.
+Prints one JSON line. --gpus N > 1 is refused: this build runs on one GPU.
 """
 
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -28,8 +29,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "QMC sample·dims/sec at n=16384 (FP64 vs BF16-MFMA); p50/p99 latency per prob"
-PEAK_FP64_VALU = 78.6e12    # FP64 vector FLOP/s of an MI355X (256 CU x 2.4 GHz x 128)
-PEAK_HBM = 8.0e12           # bytes/s
+PEAK_FP64_VALU = 78.6e12    # 256 CU x 2.4 GHz x 64 lanes x 2 flops (FMA)
+PEAK_BF16_MFMA = 2.5e15     # dense
+# FP64 operations per variable of the sweep beyond the row products (Phi, log,
+# Phi^-1, lattice point, bookkeeping); see the design doc section 5.
+C_PHI = 150
 
 
 def parse():
@@ -39,27 +43,61 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--precision", type=int, default=-1, help="-1 = the workload's own form")
+    ap.add_argument("--no-fp64-form", action="store_true", help="skip timing the FP64 form beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-samples", type=int, default=128)
+    ap.add_argument("--cpu-samples", type=int, default=384)
     return ap.parse_args()
 
 
-def sweep_flops(st: dict, m: int, n: int) -> float:
-    """Algorithmic FP64 flops of one sample through all diagonal-tile sweeps:
-    the triangular row products (2 per entry below the diagonal) plus
-    C_PHI per variable for Phi, log and Phi^-1."""
-    r = (n + m - 1) // m
-    tri = 0
-    for i in range(r):
-        mi = min(m, n - i * m)
-        tri += mi * (mi - 1)
-    return tri + C_PHI * n
+def kernel_work(kind: str, st: dict, n: int, m: int, precision: int) -> tuple[float, str]:
+    """Algorithmic work per sample of all launches of one kernel kind, and its bound."""
+    if kind == "sweep":
+        tri = sum(min(m, n - i * m) * (min(m, n - i * m) - 1) for i in range((n + m - 1) // m))
+        return tri + C_PHI * n, "alu"
+    if kind in ("delta", "zproj"):
+        f = 2.0 * m * st["k_tot"]
+        return (3 * f, "mfma") if precision == 1 else (f, "alu")
+    return float("nan"), "alu"
 
 
-# FP64 operations per variable in the common path of the one-sided step
-# (erfcx polynomial and division, exp, two logs, the Phi^-1 polynomial and
-# the bookkeeping), counted from the generated code; see DESIGN.md.
-C_PHI = 150
+def time_form(T, ctx, F, c, precision, steps, warmup):
+    N, M, nu = c["N"], c["M"], c["nu"]
+
+    def step(profile=False):
+        return T.probability(ctx, F, c["a"], c["b"], N, M, c["seed_shift"], nu=nu, precision=precision,
+                             profile=profile)
+
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    lat, results = [], []
+    t_start = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        results.append(step(profile=True))
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    return elapsed, lat, results
+
+
+def roofline_of(T, results, st, c, precision, steps):
+    n, m, samples = c["n"], c["m"], c["N"] * c["M"]
+    ks = {k: sum(r["kernel_seconds"][k] for r in results) for k in T.KERNEL_NAMES}
+    kb = {k: sum(r["kernel_busy_seconds"][k] for r in results) for k in T.KERNEL_NAMES}
+    kl = {k: sum(r["kernel_launches"][k] for r in results) for k in T.KERNEL_NAMES}
+    dom = max(kb, key=kb.get)
+    work, bound = kernel_work(dom, st, n, m, precision)
+    achieved = work * samples * steps / kb[dom]
+    peak = PEAK_BF16_MFMA if bound == "mfma" else PEAK_FP64_VALU
+    return {"bound": bound, "kernel": dom, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": None,
+            "work_per_launch_tflop": work * samples * steps / max(kl[dom], 1) / 1e12,
+            "avg_launch_ms": 1e3 * ks[dom] / max(kl[dom], 1),
+            "busy_ms_per_step": {k: 1e3 * v / steps for k, v in kb.items()},
+            "launch_ms_sum_per_step": {k: 1e3 * v / steps for k, v in ks.items()},
+            "launches_per_step": {k: kl[k] // steps for k in kl}}
 
 
 def main():
@@ -85,70 +123,50 @@ def main():
     st = F.stats()
     torch.cuda.empty_cache()
 
-    def step(profile=False):
-        return T.probability(ctx, F, c["a"], c["b"], N, M, c["seed_shift"], nu=nu,
-                             precision=precision, profile=profile)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    lat, results = [], []
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        results.append(step(profile=True))
-        lat.append(time.perf_counter() - ts)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
+    elapsed, lat, results = time_form(T, ctx, F, c, precision, args.steps, args.warmup)
     ms_per_step = 1e3 * elapsed / args.steps
     value = N * M * n / (elapsed / args.steps)
+    roof = roofline_of(T, results, st, c, precision, args.steps)
+    dev_s = float(np.mean([r["seconds"] for r in results]))
 
-    # dominant kernel and its roofline from the HIP events of the timed steps
-    ks = {k: sum(r["kernel_seconds"][k] for r in results) for k in T.KERNEL_NAMES}
-    kl = {k: sum(r["kernel_launches"][k] for r in results) for k in T.KERNEL_NAMES}
-    dom = max(ks, key=ks.get)
-    per_launch = ks[dom] / max(kl[dom], 1)
-    samples = N * M
-    if dom == "sweep":
-        work = sweep_flops(st, m, n) * samples / ((n + m - 1) // m)   # flops per launch
-    elif dom in ("delta", "zproj"):
-        work = 2.0 * m * st["k_tot"] * samples / max(kl[dom] / args.steps, 1)
-    else:
-        work = float("nan")
-    achieved = work / per_launch
-    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU, "traffic": None,
-                "avg_launch_ms": 1e3 * per_launch,
-                "kernel_ms_per_step": {k: 1e3 * v / args.steps for k, v in ks.items()}}
+    fp64 = None
+    if precision != 0 and not args.no_fp64_form:
+        e64, lat64, res64 = time_form(T, ctx, F, c, 0, max(2, args.steps // 2), 1)
+        s64 = max(2, args.steps // 2)
+        r64 = res64[-1]
+        fp64 = {"value": N * M * n / (e64 / s64), "ms_per_step": 1e3 * e64 / s64, "log_p": r64["log_p"],
+                "std_err": r64["std_err"], "rel_err": r64["rel_err"],
+                "roofline": roofline_of(T, res64, st, c, 0, s64)}
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(F, c, args.cpu_samples)
-
+    cpu = None if args.no_cpu_baseline else cpu_baseline(F, c, args.cpu_samples)
     r0 = results[-1]
-    lat_ms = sorted(1e3 * x for x in lat)
+    lat_ms = [1e3 * x for x in lat]
     out = {
         "metric": METRIC, "value": value, "unit": "sample·dims/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if precision == 0 else "bf16x3+f64",
+        "dtype": "f64" if precision == 0 else "f64+bf16",
         "data": "synthetic (seeded grid, limits and shifts)",
         "config": {"workload": f"{c['name']}: {c['g']}x{c['g']} grid, range {c['beta']}, "
-                               f"{'nu ' + str(nu) if nu else 'MVN'}, m {m}, tol {c['tol']}, "
-                               f"cap {c['cap']}, reorder {c['reorder']}, N {N} x {M} shifts",
+                               f"{'MVT nu ' + str(nu) if nu else 'MVN'}, m {m}, tol {c['tol']}, "
+                               f"cap {c['cap']}, reorder {c['reorder']}, N {N} x {M} shifts, "
+                               f"{'FP64' if precision == 0 else 'BF16x3-MFMA low-rank / FP64 sweep'}",
                    "n": n, "m": m, "samples": N, "shifts": M, "precision": precision,
                    "k_tot": st["k_tot"], "k_max": st["k_max"], "cap_hits": st["cap_hits"],
                    "factor_mb": st["device_bytes"] / 2 ** 20, "setup_s": setup_s},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
-        "estimate": {"log_p": r0["log_p"], "rel_err": r0["rel_err"], "device_s": r0["seconds"]},
-        "roofline": roofline,
+        "estimate": {"log_p": r0["log_p"], "std_err": r0["std_err"], "rel_err": r0["rel_err"]},
+        "value_device_only": N * M * n / dev_s,
+        "fp64_form": fp64,
+        "ratio_vs_fp64_form": (value / fp64["value"]) if fp64 else None,
+        "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(F, c, S: int):
-    """The oracle (dense SOV on the same factor) on the host, for S samples of shift 0."""
+    """The oracle (dense SOV on the expanded factor) on the host, S points of shift 0."""
     import oracle
     try:
         from threadpoolctl import threadpool_info
@@ -164,7 +182,7 @@ def cpu_baseline(F, c, S: int):
     t = time.perf_counter() - t0
     return {"value": S * c["n"] / t, "unit": "sample·dims/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{S} lattice points of shift 0 of the same workload (dense SOV over the expanded "
-                      f"factor), {t:.1f} s"}
+                      f"factor, numpy/scipy), {t:.1f} s"}
 
 
 if __name__ == "__main__":

@@ -189,13 +189,17 @@ enum { TLRQMC_KERNEL_INIT = 0, TLRQMC_KERNEL_DELTA = 1, TLRQMC_KERNEL_SWEEP = 2,
  * p = exp(log_p) (may underflow to 0).  n_dead counts samples whose
  * integrand is exactly 0.  seconds: device time of the estimator (lattice,
  * sweep, low-rank updates and reductions; setup excluded, as the paper
- * times only the integration, Section 4). */
+ * times only the integration, Section 4).  With opts.profile:
+ * kernel_seconds sums the launch durations of each kernel kind and
+ * kernel_busy_seconds is the union of its launch intervals (launches on the
+ * worker streams overlap). */
 typedef struct {
   double log_p, p, std_err, rel_err;
   double log_p_shift[64];
   int64_t n_dead;
   double seconds;
   double kernel_seconds[TLRQMC_KERNEL_KINDS];
+  double kernel_busy_seconds[TLRQMC_KERNEL_KINDS];
   int64_t kernel_launches[TLRQMC_KERNEL_KINDS];
   int32_t n_shifts;
   int32_t chunks;

@@ -5,6 +5,7 @@
 // update of tile j, the SOV sweep of its rows and the rank-space projection
 // of its y values, then one reduction per shift.  Student-t problems
 // (Section 2.2, Eq. 4) add a per-sample chi radius computed at chunk start.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -100,16 +101,39 @@ struct Profiler {
     (void)hipEventRecord(e, s);
     marks.push_back({open_kind, {open_ev, e}});
   }
-  void collect(tlrqmc_result *r) {
+  // Sum of launch durations and, per kind, the union of the launch
+  // intervals (launches on different streams may overlap), both measured
+  // from the reference event ref.
+  void collect(tlrqmc_result *r, hipEvent_t ref) {
+    std::vector<std::vector<std::pair<float, float>>> iv(TLRQMC_KERNEL_KINDS);
     for (int k = 0; k < TLRQMC_KERNEL_KINDS; ++k) {
       r->kernel_seconds[k] = 0.0;
+      r->kernel_busy_seconds[k] = 0.0;
       r->kernel_launches[k] = 0;
     }
     for (auto &m : marks) {
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, m.second.first, m.second.second);
-      r->kernel_seconds[m.first] += ms * 1e-3;
+      float t0 = 0.f, t1 = 0.f;
+      (void)hipEventElapsedTime(&t0, ref, m.second.first);
+      (void)hipEventElapsedTime(&t1, ref, m.second.second);
+      r->kernel_seconds[m.first] += (t1 - t0) * 1e-3;
       r->kernel_launches[m.first] += 1;
+      iv[m.first].push_back({t0, t1});
+    }
+    for (int k = 0; k < TLRQMC_KERNEL_KINDS; ++k) {
+      auto &v = iv[k];
+      std::sort(v.begin(), v.end());
+      double busy = 0.0, cs = -1.0, ce = -1.0;
+      for (auto &x : v) {
+        if (x.first > ce) {
+          if (ce > cs) busy += ce - cs;
+          cs = x.first;
+          ce = x.second;
+        } else if (x.second > ce) {
+          ce = x.second;
+        }
+      }
+      if (ce > cs) busy += ce - cs;
+      r->kernel_busy_seconds[k] = busy * 1e-3;
     }
   }
 };
@@ -358,7 +382,7 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
       if (reduce) finish_estimate(part, M, N, out);
       out->seconds = ms * 1e-3;
       out->chunks = chunks;
-      prof.collect(out);
+      prof.collect(out, ev0);
     }
   }
   return TLRQMC_OK;

@@ -57,7 +57,7 @@ class Result(C.Structure):
     _fields_ = [("log_p", C.c_double), ("p", C.c_double), ("std_err", C.c_double),
                 ("rel_err", C.c_double), ("log_p_shift", C.c_double * 64), ("n_dead", C.c_int64),
                 ("seconds", C.c_double), ("kernel_seconds", C.c_double * 5),
-                ("kernel_launches", C.c_int64 * 5), ("n_shifts", C.c_int32), ("chunks", C.c_int32)]
+                ("kernel_busy_seconds", C.c_double * 5), ("kernel_launches", C.c_int64 * 5), ("n_shifts", C.c_int32), ("chunks", C.c_int32)]
 
 
 _lib = None
@@ -292,6 +292,7 @@ def _result(res: Result, status: int) -> dict:
                log_p_shift=np.array(res.log_p_shift[:M]), n_dead=res.n_dead, seconds=res.seconds,
                chunks=res.chunks, status=status)
     out["kernel_seconds"] = {KERNEL_NAMES[k]: res.kernel_seconds[k] for k in range(5)}
+    out["kernel_busy_seconds"] = {KERNEL_NAMES[k]: res.kernel_busy_seconds[k] for k in range(5)}
     out["kernel_launches"] = {KERNEL_NAMES[k]: res.kernel_launches[k] for k in range(5)}
     return out
 
