@@ -334,7 +334,7 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
                        d_b + f->toff[j], (has_delta && !prec) ? L.Dl : nullptr,
                        (has_delta && prec) ? L.DlF : nullptr, L.R, f->d_gen, d_D, d_logp + c0, L.Y};
         prof.begin(TLRQMC_KERNEL_SWEEP, L.s);
-        launch_sweep(L.s, sp, two_sided, nu > 0);
+        launch_sweep(L.s, sp, two_sided, nu > 0, prec);
         prof.end(L.s);
         if (!check_launch("sweep")) return fail_device(ctx, lanes.size());
         if (j < r - 1 && f->kcol[j] > 0) {

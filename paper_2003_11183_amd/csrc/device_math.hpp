@@ -94,8 +94,8 @@ __device__ __forceinline__ double exp_nonpos(ctab_t T, double x) {
 // (exact), s = f / (2 + f), log m = 2s + s^3 Q(s^2).
 __device__ __forceinline__ double log_pos(ctab_t T, double x) {
   if (!(x > 0.0) || isinf(x)) return x == 0.0 ? -INFINITY : (x > 0.0 ? x : NAN);
-  int e;
-  double m = frexp(x, &e);
+  int e = __builtin_amdgcn_frexp_exp(x);
+  double m = __builtin_amdgcn_frexp_mant(x);
   if (m < M_SQRT1_2) {
     m *= 2.0;
     e -= 1;
@@ -189,17 +189,21 @@ __device__ inline double Phi_inv(ctab_t T, double u) {
   return M_SQRT2 * x * inv_poly(T, wv);
 }
 
-// Phi^-1(exp(lu)) for lu possibly far below the double range.
+// Phi^-1(exp(lu)) for lu possibly far below the double range.  Above
+// lu = -690 this is Phi_inv(exp(lu)).  Below, 1 - u = 1 to double
+// precision, so w = -log(4 u (1 - u)) = -log 4 - lu and the tail polynomial
+// applies up to w = 756 (lu = -757); further out, Newton steps on log Phi
+// from the asymptotic start, with log Phi(y) = log(erfcx(-y/sqrt2)/2) -
+// y^2/2 and erfcx from its asymptotic series (-y/sqrt2 > 12 there).
 __device__ inline double Phi_inv_log(ctab_t T, double lu) {
-  if (lu > -700.0) return Phi_inv(T, exp_nonpos(T, lu));
-  const double wv = -kLog4 - lu;  // -log(4 u (1 - u)) with 1 - u = 1
+  if (lu > -690.0) return Phi_inv(T, exp_nonpos(T, lu));
+  const double wv = -kLog4 - lu;
   if (wv <= 756.25) return -M_SQRT2 * inv_poly(T, wv);
-  // Asymptotic start from log Phi(y) ~ -y^2/2 - log(-y) - log(2 pi)/2, then
-  // Newton steps on log Phi(y) - lu, whose derivative is phi(y) / Phi(y).
-  double y = -sqrt(-2.0 * lu - log(-4.0 * M_PI * lu));
+  double y = -sqrt(-2.0 * lu - log_pos(T, -4.0 * M_PI * lu));
   for (int it = 0; it < 12; ++it) {
-    const double lp = log_Phi(T, y);
-    const double dy = (lp - lu) / exp(-0.5 * y * y - kLogSqrt2Pi - lp);
+    const double z = -y * M_SQRT1_2;
+    const double lp = log_pos(T, 0.5 * erfcx_large(z)) - z * z;
+    const double dy = (lp - lu) / exp_nonpos(T, -z * z - kLogSqrt2Pi - lp);
     y -= dy;
     if (fabs(dy) <= 1e-16 * fabs(y)) break;
   }
@@ -286,6 +290,46 @@ __device__ inline double sov_step_upper(double bh, double w, double &y) {
     y = Phi_inv(T, w * e);
   } else {
     y = Phi_inv_log(T, log_pos(T, w) + le);
+  }
+  return le;
+}
+
+template <int N>
+__device__ __forceinline__ float horner32(const float (&c)[N], float s) {
+  float acc = c[N - 1];
+#pragma unroll
+  for (int i = N - 2; i >= 0; --i) acc = fmaf(acc, s, c[i]);
+  return acc;
+}
+
+// Precision form of the one-sided step: Phi(bh), log Phi(bh) and the
+// quantile in FP32 in the centre (|bh| <= 11, w' = -log(4u(1-u)) < 6.25),
+// with the FP64 path for the tails.  The running sum of log P stays FP64;
+// the FP32 parts carry about 1e-7 relative error, far below the QMC error.
+__device__ inline double sov_step_upper_mixed(double bh, double w, double &y) {
+  const double ab = fabs(bh);
+  if (!(ab <= 11.0)) return sov_step_upper(bh, w, y);
+  const float z = static_cast<float>(ab * M_SQRT1_2);
+  const float t = (z - kErfcx32K) * __builtin_amdgcn_rcpf(z + kErfcx32K);
+  const float g = horner32(kErfcx32, (t - kErfcx32C) * kErfcx32H);
+  const float ex = g * (1.0f - t) * 0.25f;  // erfcx(z) / 2
+  const double p = bh * bh;
+  const double a = 0.5 * p;
+  const double al = 0.5 * fma(bh, bh, -p);
+  const float q = ex * __builtin_amdgcn_exp2f(static_cast<float>(-(a + al) * M_LOG2E));
+  const bool neg = bh < 0.0;
+  const float e = neg ? q : 1.0f - q;
+  // log of ex (below zero) or of 1 - q (above): one hardware log2
+  const float lg = __builtin_amdgcn_logf(neg ? ex : e) * static_cast<float>(M_LN2);
+  const double le = neg ? static_cast<double>(lg) - a - al : static_cast<double>(lg);
+  const double u = w * static_cast<double>(e);
+  const double q4 = 4.0 * u * (1.0 - u);
+  const float wv = -__builtin_amdgcn_logf(static_cast<float>(q4)) * static_cast<float>(M_LN2);
+  if (wv < 6.25f) {
+    const float pw = horner32(kInv32, (wv - kInv32C) * kInv32H);
+    y = M_SQRT2 * (2.0 * u - 1.0) * static_cast<double>(pw);
+  } else {
+    y = Phi_inv(special_table(), u);
   }
   return le;
 }

@@ -132,35 +132,36 @@ int factor_build(tlrqmc_ctx *ctx, int64_t n, int m, const int32_t *perm, const d
     for (double v : f->h_V)
       if (!std::isfinite(v)) return fail(TLRQMC_EINVAL, "non-finite entry in V");
   }
-  // ---- blocked diagonal tiles
+  // ---- blocked diagonal tiles (row blocks of SB, see the sweep kernel)
+  constexpr int SB = kSweepBlock;
   std::vector<double> hb;
   f->diag_off.assign(r + 1, 0);
   {
     int64_t o = 0;
     for (int i = 0; i < r; ++i) {
       const int mi = f->tm[i];
-      const int nb = (mi + 31) / 32;
+      const int nb = (mi + SB - 1) / SB;
       f->diag_off[i] = static_cast<int64_t>(hb.size());
-      hb.resize(hb.size() + static_cast<size_t>(nb) * (nb + 1) / 2 * 1024, 0.0);
+      hb.resize(hb.size() + static_cast<size_t>(nb) * (nb + 1) / 2 * SB * SB, 0.0);
       double *T = hb.data() + f->diag_off[i];
       const double *src = f->h_diag.data() + o;
       auto Bat = [&](int t, int u) { return src[static_cast<int64_t>(t) * mi + u]; };
       for (int q = 0; q < nb; ++q) {
         for (int pb = 0; pb <= q; ++pb) {
-          double *blk = T + (static_cast<int64_t>(q) * (q + 1) / 2 + pb) * 1024;
+          double *blk = T + (static_cast<int64_t>(q) * (q + 1) / 2 + pb) * SB * SB;
           if (pb < q) {
-            for (int u = 0; u < 32; ++u)
-              for (int t = 0; t < 32; ++t) {
-                const int row = 32 * q + t, c = 32 * pb + u;
-                blk[u * 32 + t] = row < mi ? Bat(row, c) : 0.0;
+            for (int u = 0; u < SB; ++u)
+              for (int t = 0; t < SB; ++t) {
+                const int row = SB * q + t, c = SB * pb + u;
+                blk[u * SB + t] = row < mi ? Bat(row, c) : 0.0;
               }
           } else {
-            for (int t = 0; t < 32; ++t) {
-              const int row = 32 * q + t;
+            for (int t = 0; t < SB; ++t) {
+              const int row = SB * q + t;
               if (row >= mi) continue;
-              blk[t * 32] = 1.0 / Bat(row, row);
-              for (int ii = 1; t + ii < 32; ++ii)
-                if (row + ii < mi) blk[t * 32 + ii] = Bat(row + ii, row);
+              blk[t * SB] = 1.0 / Bat(row, row);
+              for (int ii = 1; t + ii < SB; ++ii)
+                if (row + ii < mi) blk[t * SB + ii] = Bat(row + ii, row);
             }
           }
         }

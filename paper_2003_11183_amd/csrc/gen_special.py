@@ -140,6 +140,35 @@ def log_q(v):
     return (mp.log((1 + sq) / (1 - sq)) - 2 * sq) / (sq ** 3)
 
 
+# FP32 centre-region forms of the precision variant (coefficients rounded to
+# float32; checked by float32 Horner evaluation).
+Z_MAX32 = 8.0
+K32 = 2.5
+T_MAX32 = (Z_MAX32 - K32) / (Z_MAX32 + K32)
+DEG32_ERFCX = 11
+DEG32_INV = 10
+W_MAX32 = 6.25
+
+
+def erfcx_scaled_t32(t):
+    z = K32 * (1 + t) / (1 - t)
+    return mp.exp(z * z) * mp.erfc(z) * (z + K32) / K32
+
+
+def fit32(f, a, b, deg, name):
+    cf, c, h = cheb_fit(f, a, b, deg)
+    c32 = [float(np.float32(x)) for x in cf]
+    xs = np.linspace(a, b, 3001)
+    s = ((xs - c) / h).astype(np.float32)
+    acc = np.float32(c32[-1]) + np.zeros_like(s)
+    for cc in reversed(c32[:-1]):
+        acc = (acc * s + np.float32(cc)).astype(np.float32)
+    ref = np.array([float(f(mp.mpf(x))) for x in xs])
+    err = float(np.max(np.abs(acc.astype(np.float64) - ref) / np.abs(ref)))
+    print(f"// {name} (float32): degree {deg}, max relative error {err:.2e}", file=sys.stderr)
+    return c32, c, h
+
+
 def asym_check():
     """Worst relative error of the truncated asymptotic series at z >= Z_MAX."""
     worst = 0.0
@@ -193,6 +222,14 @@ def main():
     out.append(f"constexpr double kLogC = {ml!r}, kLogH = {1.0 / hl!r};  // (s^2 - C) * H")
     out.append(f"constexpr int kOffLog = {len(table)}, kNLog = {len(cl)};")
     table += cl
+    # float32 polynomials (compile-time constants: 32-bit literals in the code)
+    c32e, m32e, h32e = fit32(erfcx_scaled_t32, -1, T_MAX32, DEG32_ERFCX, "erfcx g(t), z in [0, 8]")
+    c32i, m32i, h32i = fit32(erfinv_p_of_w, 0.0, W_MAX32, DEG32_INV, "erfinv p(w), w in [0, 6.25]")
+    out.append(f"constexpr float kErfcx32K = {K32!r}f, kErfcx32Zmax = {Z_MAX32!r}f;")
+    out.append(f"constexpr float kErfcx32C = {float(np.float32(m32e))!r}f, kErfcx32H = {float(np.float32(1.0 / h32e))!r}f;")
+    out.append(f"constexpr float kErfcx32[{len(c32e)}] = {{" + ", ".join(f"{x!r}f" for x in c32e) + "};")
+    out.append(f"constexpr float kInv32C = {float(np.float32(m32i))!r}f, kInv32H = {float(np.float32(1.0 / h32i))!r}f;")
+    out.append(f"constexpr float kInv32[{len(c32i)}] = {{" + ", ".join(f"{x!r}f" for x in c32i) + "};")
     body = ",\n    ".join(f"{x:.17e}" for x in table)
     out.append(f"constexpr int kSpecialTableSize = {len(table)};")
     out.append(f"TLRQMC_SPECIAL_TABLE double kSpecialTable[{len(table)}] = {{\n    {body}}};")

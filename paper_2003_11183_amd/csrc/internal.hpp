@@ -17,7 +17,7 @@ void clear_error();
 
 // Row-block height of the diagonal-tile sweep and the padded row count of a
 // tile in the blocked layout.
-constexpr int kSweepBlock = 32;
+constexpr int kSweepBlock = 16;
 // Rows (delta) / columns (projection) produced per FP64 low-rank pass.
 constexpr int kLrRows = 64;
 
@@ -157,7 +157,7 @@ int delta_mfma_rt(int rows);
 void launch_delta_mfma(hipStream_t s, const MfmaDeltaParams &p);
 void launch_zproj_mfma(hipStream_t s, const MfmaZprojParams &p);
 void launch_init(hipStream_t s, const InitParams &p);
-void launch_sweep(hipStream_t s, const SweepParams &p, bool two_sided, bool scaled);
+void launch_sweep(hipStream_t s, const SweepParams &p, bool two_sided, bool scaled, bool mixed);
 void launch_delta_f64(hipStream_t s, const LrParams &p);
 void launch_zproj_f64(hipStream_t s, const LrParams &p);
 void launch_reduce(hipStream_t s, const ReduceParams &p, int n_shifts);

@@ -39,19 +39,20 @@ __global__ __launch_bounds__(256) void k_init(InitParams p) {
 }
 
 // --------------------------------------------------------------- sweep ----
-// Blocked tile layout (row blocks of 32): for row block q the blocks
-// (q, 0..q) are stored consecutively, 1024 doubles each, starting at block
-// index q(q+1)/2.  An off-diagonal block (q, p) is column-major: entry
-// [u*32 + t] = B(32q + t, 32p + u).  The diagonal block is stored by
-// columns as well, entry [t*32 + i] = B(32q + t + i, 32q + t) for i >= 1
-// (zero past the block) and entry [t*32] = 1 / B(32q + t, 32q + t).
+// Blocked tile layout (row blocks of SB = kSweepBlock): for row block q the
+// blocks (q, 0..q) are stored consecutively, SB*SB doubles each, starting
+// at block index q(q+1)/2.  An off-diagonal block (q, p) is column-major:
+// entry [u*SB + t] = B(SB q + t, SB p + u).  The diagonal block is stored by
+// columns as well, entry [t*SB + i] = B(SB q + t + i, SB q + t) for i >= 1
+// (zero past the block) and entry [t*SB] = 1 / B(SB q + t, SB q + t).
 //
 // Within a row block the recursion is right looking: acc[i] holds the
 // partial row sum of row t + i; after y_t is known the column below the
 // diagonal is added and the window slides down by one, so every index into
 // acc is a compile-time constant and acc stays in registers.
-template <bool TWO_SIDED, bool SCALED>
+template <bool TWO_SIDED, bool SCALED, bool MIXED>
 __global__ __launch_bounds__(256) void k_sweep(SweepParams p) {
+  constexpr int SB = kSweepBlock;
   const int64_t si = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   if (si >= p.count) return;
   const int64_t g = p.g0 + si;
@@ -67,45 +68,53 @@ __global__ __launch_bounds__(256) void k_sweep(SweepParams p) {
   const double *Dl = p.Delta ? p.Delta + si : nullptr;
   const float *DlF = p.DeltaF ? p.DeltaF + si : nullptr;
   double lp = p.logp[si];
-  const int nb = (p.mj + 31) >> 5;
+  const int nb = (p.mj + SB - 1) / SB;
   auto blk = as_const(p.B);
   for (int q = 0; q < nb; ++q) {
-    double acc[32];
+    double acc[SB];
 #pragma unroll
-    for (int t = 0; t < 32; ++t) acc[t] = 0.0;
-    for (int pb = 0; pb < q; ++pb, blk += 1024) {
-      const double *Yp = Y + static_cast<int64_t>(pb) * 32 * ld;
-#pragma unroll 4
-      for (int u = 0; u < 32; ++u) {
+    for (int t = 0; t < SB; ++t) acc[t] = 0.0;
+    for (int pb = 0; pb < q; ++pb, blk += SB * SB) {
+      const double *Yp = Y + static_cast<int64_t>(pb) * SB * ld;
+#pragma unroll 8
+      for (int u = 0; u < SB; ++u) {
         const double yv = Yp[u * ld];
 #pragma unroll
-        for (int t = 0; t < 32; ++t) acc[t] = fma(blk[u * 32 + t], yv, acc[t]);
+        for (int t = 0; t < SB; ++t) acc[t] = fma(blk[u * SB + t], yv, acc[t]);
       }
     }
-    const int rows = min(32, p.mj - q * 32);
-    for (int t = 0; t < rows; ++t) {
-      const int row = q * 32 + t;
-      const auto col = blk + t * 32;
-      double bt = R * bl[row];
-      double dlt = 0.0;
-      if (Dl) dlt = Dl[row * ld];
-      if (DlF) dlt = static_cast<double>(DlF[row * ld]);
-      bt -= dlt;
-      const double w = lattice_point(k, Ag[row], Ds[row]);
+    const int rows = min(SB, p.mj - q * SB);
+    // Per-lane operands of the next row (shift word, low-rank update) are
+    // loaded one row ahead so that their memory latency overlaps the
+    // current row's special functions.
+    int row = q * SB;
+    uint64_t dnext = Ds[row];
+    double dlnext = Dl ? Dl[row * ld] : (DlF ? static_cast<double>(DlF[row * ld]) : 0.0);
+    for (int t = 0; t < rows; ++t, ++row) {
+      const uint64_t dcur = dnext;
+      const double dlt = dlnext;
+      if (t + 1 < rows) {
+        dnext = Ds[row + 1];
+        dlnext = Dl ? Dl[(row + 1) * ld] : (DlF ? static_cast<double>(DlF[(row + 1) * ld]) : 0.0);
+      }
+      const auto col = blk + t * SB;
+      const double bt = R * bl[row] - dlt;
+      const double w = lattice_point(k, Ag[row], dcur);
       double y, ldel;
       if (TWO_SIDED) {
         const double at = R * al[row] - dlt;
         ldel = sov_step((at - acc[0]) * col[0], (bt - acc[0]) * col[0], w, y);
       } else {
-        ldel = sov_step_upper((bt - acc[0]) * col[0], w, y);
+        ldel = MIXED ? sov_step_upper_mixed((bt - acc[0]) * col[0], w, y)
+                     : sov_step_upper((bt - acc[0]) * col[0], w, y);
       }
       lp += ldel;
       Y[row * ld] = y;
 #pragma unroll
-      for (int i = 1; i < 32; ++i) acc[i - 1] = fma(col[i], y, acc[i]);
-      acc[31] = 0.0;
+      for (int i = 1; i < SB; ++i) acc[i - 1] = fma(col[i], y, acc[i]);
+      acc[SB - 1] = 0.0;
     }
-    blk += 1024;
+    blk += SB * SB;
   }
   p.logp[si] = lp;
 }
@@ -216,14 +225,17 @@ void launch_init(hipStream_t s, const InitParams &p) {
   hipLaunchKernelGGL(k_init, dim3(grid_of(p.count)), dim3(256), 0, s, p);
 }
 
-void launch_sweep(hipStream_t s, const SweepParams &p, bool two_sided, bool scaled) {
+void launch_sweep(hipStream_t s, const SweepParams &p, bool two_sided, bool scaled, bool mixed) {
   const dim3 grid(grid_of(p.count)), block(256);
   if (two_sided) {
-    if (scaled) hipLaunchKernelGGL((k_sweep<true, true>), grid, block, 0, s, p);
-    else hipLaunchKernelGGL((k_sweep<true, false>), grid, block, 0, s, p);
+    if (scaled) hipLaunchKernelGGL((k_sweep<true, true, false>), grid, block, 0, s, p);
+    else hipLaunchKernelGGL((k_sweep<true, false, false>), grid, block, 0, s, p);
+  } else if (mixed) {
+    if (scaled) hipLaunchKernelGGL((k_sweep<false, true, true>), grid, block, 0, s, p);
+    else hipLaunchKernelGGL((k_sweep<false, false, true>), grid, block, 0, s, p);
   } else {
-    if (scaled) hipLaunchKernelGGL((k_sweep<false, true>), grid, block, 0, s, p);
-    else hipLaunchKernelGGL((k_sweep<false, false>), grid, block, 0, s, p);
+    if (scaled) hipLaunchKernelGGL((k_sweep<false, true, false>), grid, block, 0, s, p);
+    else hipLaunchKernelGGL((k_sweep<false, false, false>), grid, block, 0, s, p);
   }
 }
 
