@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-fp64-form", action="store_true", help="skip timing the FP64 form beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=384)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (scale for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -107,6 +109,9 @@ def main():
                                    "(multi-GPU sharding is described in DESIGN.md, not built)"}))
         sys.exit(2)
     import torch
+    if args.copy_calibration > 0:
+        copy_calibration(torch, args.copy_calibration)
+        return
 
     import synth
     from paper_2003_11183_amd import tlrqmc as T
@@ -163,6 +168,17 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def copy_calibration(torch, mib: int):
+    """A plain device-to-device copy of known size: what the HBM byte counters read for it scales theirs."""
+    n = mib * 2 ** 20 // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 3}}), flush=True)
 
 
 def cpu_baseline(F, c, S: int):

@@ -318,9 +318,9 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
           prof.begin(TLRQMC_KERNEL_DELTA, L.s);
           if (prec) {
             const unsigned short *u = f->d_ubf + f->ubf_off[j];
-            MfmaDeltaParams mp{cnt, ld, f->tm[j], static_cast<int>(f->krow[j]), f->kp_row[j], u,
-                               u + f->ubf_size[j], L.ZF + f->zoffp[j] * ld, L.DlF};
-            launch_delta_mfma(L.s, mp);
+            MfmaLrParams mp{cnt, ld, f->tm[j], static_cast<int>(f->krow[j]), f->kp_row[j], u,
+                            u + f->ubf_size[j], L.ZF + f->zoffp[j] * ld, nullptr, nullptr, L.DlF};
+            launch_lr_mfma(L.s, mp);
           } else {
             LrParams lp{cnt, ld, f->tm[j], static_cast<int>(f->krow[j]), f->urow_ld[j],
                         f->d_urow + f->urow_off[j], L.Z + f->zoff[j] * ld, L.Dl, nullptr};
@@ -341,9 +341,9 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
           prof.begin(TLRQMC_KERNEL_ZPROJ, L.s);
           if (prec) {
             const unsigned short *v = f->d_vbf + f->vbf_off[j];
-            MfmaZprojParams zp{cnt, ld, f->tm[j], f->vbf_mp[j], static_cast<int>(f->kcol[j]), v,
-                               v + f->vbf_size[j], L.Y, f->d_zmapp + f->zmap_off[j], L.ZF};
-            launch_zproj_mfma(L.s, zp);
+            MfmaLrParams zp{cnt, ld, static_cast<int>(f->kcol[j]), f->tm[j], f->vbf_mp[j], v,
+                            v + f->vbf_size[j], nullptr, L.Y, f->d_zmapp + f->zmap_off[j], L.ZF};
+            launch_lr_mfma(L.s, zp);
           } else {
             LrParams lp{cnt, ld, static_cast<int>(f->kcol[j]), f->tm[j], f->vpan_ld[j],
                         f->d_vpan + f->vpan_off[j], L.Y, L.Z, f->d_zmap + f->zmap_off[j]};

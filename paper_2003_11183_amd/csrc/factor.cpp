@@ -241,8 +241,7 @@ int factor_build(tlrqmc_ctx *ctx, int64_t n, int m, const int32_t *perm, const d
   f->ubf_off.assign(r + 1, 0);
   f->ubf_size.assign(r, 0);
   for (int i = 0; i < r; ++i) {
-    const int rt = delta_mfma_rt(f->tm[i]);
-    const int64_t rows = round_up(f->tm[i], 64 * rt);
+    const int64_t rows = lr_mfma_rows(f->tm[i]);
     const int64_t kp = f->kp_row[i];
     f->ubf_off[i] = static_cast<int64_t>(hub.size());
     f->ubf_size[i] = rows * kp;
@@ -257,7 +256,7 @@ int factor_build(tlrqmc_ctx *ctx, int64_t n, int m, const int32_t *perm, const d
   f->vbf_size.assign(r, 0);
   f->vbf_mp.assign(r, 0);
   for (int j = 0; j < r; ++j) {
-    const int64_t kp = round_up(f->kcol[j], 32);
+    const int64_t kp = lr_mfma_rows(static_cast<int>(f->kcol[j]));
     const int64_t mp = round_up(f->tm[j], 32);
     f->vbf_mp[j] = static_cast<int>(mp);
     f->vbf_off[j] = static_cast<int64_t>(hvb.size());

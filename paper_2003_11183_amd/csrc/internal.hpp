@@ -136,26 +136,24 @@ struct ReduceParams {
   double *part;            // per shift: max, sum exp(lp - max), dead count
 };
 
-struct MfmaDeltaParams {
+// C (rows x count) = A (rows x K) B (K x count) on BF16 matrix cores.  A is
+// pre-split into BF16 hi/lo, row-major with leading dimension KP (a
+// multiple of 32), rows padded to lr_mfma_rows(rows); B is FP32 or FP64
+// with leading dimension ld.  Output row c goes to row map[c] when a map
+// is given.
+struct MfmaLrParams {
   int64_t count, ld;
-  int rows, K, KP;         // m_i, krow (valid k), krow padded to 32
-  const unsigned short *Uhi, *Ulo;
-  const float *Z;          // first padded Z row of tile i
-  float *Delta;
+  int rows, K, KP;
+  const unsigned short *Ahi, *Alo;
+  const float *Bf;         // B in FP32, or null
+  const double *Bd;        // B in FP64, or null
+  const int32_t *map;      // output row map, or null
+  float *Out;
 };
 
-struct MfmaZprojParams {
-  int64_t count, ld;
-  int mj, mp, Kc;          // tile rows, rows padded to 32, V_panel columns
-  const unsigned short *Vhi, *Vlo;
-  const double *Y;
-  const int32_t *map;
-  float *Z;
-};
-
-int delta_mfma_rt(int rows);
-void launch_delta_mfma(hipStream_t s, const MfmaDeltaParams &p);
-void launch_zproj_mfma(hipStream_t s, const MfmaZprojParams &p);
+int lr_mfma_rt(int rows);
+int64_t lr_mfma_rows(int rows);
+void launch_lr_mfma(hipStream_t s, const MfmaLrParams &p);
 void launch_init(hipStream_t s, const InitParams &p);
 void launch_sweep(hipStream_t s, const SweepParams &p, bool two_sided, bool scaled, bool mixed);
 void launch_delta_f64(hipStream_t s, const LrParams &p);
