@@ -46,6 +46,11 @@ def parse():
     ap.add_argument("--no-fp64-form", action="store_true", help="skip timing the FP64 form beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=384)
+    ap.add_argument("--serve", type=int, default=100, metavar="COUNT",
+                    help="requests of the mixed-dimension serving stream to replay (0 = skip)")
+    ap.add_argument("--serve-fp64", type=int, default=12, metavar="COUNT",
+                    help="of those, how many also run one at a time through the plain FP64 path")
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (scale for HBM byte counters)")
     return ap.parse_args()
@@ -144,6 +149,9 @@ def main():
                 "roofline": roofline_of(T, res64, st, c, 0, s64)}
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(F, c, args.cpu_samples)
+    F.free()
+    torch.cuda.empty_cache()
+    serve = serving(T, ctx, args.serve, args.serve_fp64, args.serve_budget_gib) if args.serve > 0 else None
     r0 = results[-1]
     lat_ms = [1e3 * x for x in lat]
     out = {
@@ -166,8 +174,64 @@ def main():
         "ratio_vs_fp64_form": (value / fp64["value"]) if fp64 else None,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "serving": serve,
     }
     print(json.dumps(out), flush=True)
+
+
+def serving(T, ctx, count: int, count_fp64: int, budget_gib: float):
+    """Replay the first `count` requests of the mixed-dimension stream at their
+    Poisson arrival times through the request server (continuous batching,
+    footprint admission; BF16x3-MFMA low-rank form).  Latency = done - submit.
+    The first `count_fp64` requests then also run one at a time through the
+    plain FP64 single-request path (factor + mvn_prob/mvt_prob)."""
+    import synth
+    reqs = synth.serving_stream(count=count)
+    S = T.Server(ctx, int(budget_gib * 2 ** 30))
+    t0 = time.perf_counter()
+    tickets = []
+    for q in reqs:
+        delay = q["arrival"] - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(S.submit({"xy": q["xy"], "beta": q["beta"]}, q["a"], q["b"], q["N"], q["M"], q["seed_shift"],
+                                nu=q["nu"], m=q["m"], tol=1e-5, precision=1))
+    out = [S.result(t, timeout_s=600) for t in tickets]
+    st = S.stats()
+    S.close()
+    info = [o["info"] for o in out]
+    lat = np.array([i["t_done"] - i["t_submit"] for i in info])
+    setup = np.array([i["t_ready"] - i["t_admit"] for i in info])
+    queue = np.array([i["t_admit"] - i["t_submit"] for i in info])
+    run = np.array([i["t_done"] - i["t_start"] for i in info])
+    span = max(i["t_done"] for i in info) - min(i["t_submit"] for i in info)
+    work = float(sum(q["N"] * q["M"] * q["n"] for q in reqs))
+    res = {"requests": count, "rate_per_s": 20.0, "budget_gib": budget_gib,
+           "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)), "p99": 1e3 * float(np.percentile(lat, 99)),
+                          "mean": 1e3 * float(lat.mean())},
+           "phase_ms_mean": {"queue": 1e3 * float(queue.mean()), "setup": 1e3 * float(setup.mean()),
+                             "run": 1e3 * float(run.mean())},
+           "run_ms": {"p50": 1e3 * float(np.percentile(run, 50)), "p99": 1e3 * float(np.percentile(run, 99))},
+           "throughput": work / span, "unit": "sample·dims/s", "makespan_s": span,
+           "server": {k: st[k] for k in ("steps", "launches", "slot_steps", "max_active_slots",
+                                         "peak_reserved_bytes", "arena_peak_bytes")},
+           "n_mix": {str(g * g): sum(1 for q in reqs if q["g"] == g) for g in (32, 64, 96, 128)}}
+    if count_fp64 > 0:
+        import torch
+        lat64, work64 = [], 0.0
+        t1 = time.perf_counter()
+        for q in reqs[:count_fp64]:
+            ts = time.perf_counter()
+            F = T.Factor.build(ctx, {"xy": q["xy"], "beta": q["beta"]}, q["n"], q["m"], 1e-5, 0)
+            T.probability(ctx, F, q["a"], q["b"], q["N"], q["M"], q["seed_shift"], nu=q["nu"], precision=0)
+            F.free()
+            lat64.append(time.perf_counter() - ts)
+            work64 += q["N"] * q["M"] * q["n"]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        res["fp64_one_at_a_time"] = {"requests": count_fp64, "latency_ms_mean": 1e3 * float(np.mean(lat64)),
+                                     "throughput": work64 / el, "unit": "sample·dims/s"}
+    return res
 
 
 def copy_calibration(torch, mib: int):

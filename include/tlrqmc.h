@@ -141,6 +141,10 @@ typedef struct {
   int64_t diag_doubles; /* entries of the exchange diag array        */
   int64_t uv_doubles;   /* entries of each exchange U and V array    */
   int64_t device_bytes; /* device memory held by the factor          */
+  /* tlr_factor only (0 otherwise), seconds: covariance and Cholesky on
+   * the device, transfer of the factor to the host, compression of the
+   * off-diagonal tiles, device layouts and upload. */
+  double setup_seconds[4];
 } tlrqmc_factor_info;
 
 int tlrqmc_factor_stats(const tlrqmc_factor *f, tlrqmc_factor_info *out);
@@ -224,6 +228,114 @@ int mvt_prob(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, const dou
 int tlrqmc_sample_logp(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a,
                        const double *b, double nu, const tlrqmc_qmc_opts *opts, int32_t shift,
                        int64_t k0, int64_t count, double *logp_out);
+
+/* -------------------------------------------------------------- serving --
+ * A request server answers a stream of probability requests of mixed
+ * dimension on the context's device (the likelihood evaluations of
+ * Section 5 call the estimator many times, each with its own covariance
+ * parameters and limits).  For each request it orders the variables
+ * (geometric order, or block reordering of Section 3.3), builds the TLR
+ * factor (as tlr_factor) and runs the estimator (as mvn_prob / mvt_prob).
+ *
+ * Continuous batching: a request's N * M samples are cut into slots of a
+ * size that depends on the request alone.  Each server step advances every
+ * active slot, of every request, by one diagonal tile in shared kernel
+ * launches, so requests that arrive while others run start at the next
+ * step and their work overlaps on the device.  The arithmetic of a sample
+ * does not depend on the other slots of a step and each request is reduced
+ * on its own in a fixed order: a result is the same, bit for bit, alone or
+ * in any mix.
+ *
+ * Admission by device-memory footprint: the server takes one arena of
+ * hbm_budget_bytes from the context's allocator at creation and serves
+ * every device allocation of its requests from it.  A queued request is
+ * admitted to setup, in arrival order, when the reservations held by
+ * admitted requests plus its setup footprint (the dense covariance) fit the
+ * budget.  After setup its reservation becomes its run footprint: the
+ * factor, its limits, shift table and per-sample results, and the buffers
+ * of as many slots as fit in the larger of its setup footprint and a
+ * quarter of the budget (its slot concurrency, at least one).  A request
+ * whose setup footprint or single-slot run footprint exceeds the budget
+ * fails with TLRQMC_ENOMEM.
+ *
+ * Threads: the server runs a setup thread and a step thread with two HIP
+ * streams of its own (default priority).  submit, poll and stats may be
+ * called from any thread.  The context's allocator is called only inside
+ * tlrqmc_server_create and tlrqmc_server_destroy. */
+typedef struct tlrqmc_server tlrqmc_server;
+
+/* One request.  All host arrays are copied by tlrqmc_server_submit.
+ *   n, cov        : dimension and covariance (as tlr_factor)
+ *   a, b          : limits, n entries, original order (as mvn_prob)
+ *   nu            : 0 = normal, > 0 = Student-t degrees of freedom
+ *   m, tol, max_rank : tile size and truncation (as tlr_factor)
+ *   reorder       : 1 = block reordering, 0 = geometric order
+ *   qmc           : n_samples, n_shifts, precision, seed (logp_out,
+ *                   profile and chunk_samples are ignored) */
+typedef struct {
+  int64_t n;
+  tlrqmc_cov cov;
+  const double *a;
+  const double *b;
+  double nu;
+  int32_t m;
+  int32_t max_rank;
+  double tol;
+  int32_t reorder;
+  int32_t reserved;
+  tlrqmc_qmc_opts qmc;
+} tlrqmc_request;
+
+/* Life of one request, in seconds since the server was created. */
+typedef struct {
+  double t_submit;        /* submit returned the ticket          */
+  double t_admit;         /* admitted to setup (budget)          */
+  double t_ready;         /* factor built                        */
+  double t_start;         /* first slot on the device            */
+  double t_done;          /* estimate available                  */
+  int64_t reserved_bytes; /* run reservation                     */
+  int64_t factor_bytes;
+  int64_t chunk_samples;  /* samples per slot                    */
+  int32_t slots;          /* slots of the request                */
+  int32_t concurrency;    /* slots it may have active at once    */
+  int32_t status;
+  int32_t reserved;
+} tlrqmc_request_info;
+
+typedef struct {
+  int64_t budget_bytes, reserved_bytes, peak_reserved_bytes;
+  int64_t arena_in_use_bytes, arena_peak_bytes;
+  int64_t steps;           /* server steps launched                */
+  int64_t launches;        /* kernel launches                      */
+  int64_t slot_steps;      /* sum over steps of the active slots   */
+  int64_t max_active_slots;
+  int32_t queued, in_setup, ready, running;
+} tlrqmc_server_info;
+
+/* Create a server on ctx's device with a device budget of hbm_budget_bytes
+ * (at least 16 MiB), allocated at once from ctx's allocator. */
+int tlrqmc_server_create(tlrqmc_ctx *ctx, size_t hbm_budget_bytes, tlrqmc_server **out);
+
+/* Queue a request; *ticket identifies it.  Invalid requests return
+ * TLRQMC_EINVAL at once.  A request with a_i >= b_i for some i completes
+ * at once with log_p = -inf. */
+int tlrqmc_server_submit(tlrqmc_server *s, const tlrqmc_request *req, uint64_t *ticket);
+
+/* Result of a ticket.  wait_ms = 0 returns at once, wait_ms > 0 waits up
+ * to that many milliseconds, wait_ms < 0 waits until the request is done;
+ * TLRQMC_PENDING if it is not done by then.  Once done: the request's status
+ * (TLRQMC_OK, TLRQMC_WARN_RANKCAP, or the error its setup or run met, with
+ * the message in tlrqmc_last_error) and *out, *info (either may be NULL)
+ * filled; result.seconds is the latency from submit to done.  The ticket
+ * is then released (TLRQMC_ENOTFOUND afterwards). */
+int tlrqmc_server_poll(tlrqmc_server *s, uint64_t ticket, int32_t wait_ms, tlrqmc_result *out,
+                       tlrqmc_request_info *info);
+
+int tlrqmc_server_stats(tlrqmc_server *s, tlrqmc_server_info *out);
+
+/* Finish every submitted request, stop the threads and free the arena.
+ * Results not yet polled are discarded. */
+int tlrqmc_server_destroy(tlrqmc_server *s);
 
 #ifdef __cplusplus
 }

@@ -59,7 +59,7 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError(f"compilation failed:\n{msg}")
     tmp = LIB + ".tmp"
     link = [os.path.join(ROCM, "bin", "hipcc"), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-fopenmp"] + objs + [
-        f"-L{os.path.join(ROCM, 'lib')}", "-lrocblas",
+        f"-L{os.path.join(ROCM, 'lib')}", "-lrocblas", "-lrocsolver",
         f"-Wl,-rpath,{os.path.join(ROCM, 'lib')}", f"-Wl,-rpath,{os.path.join(ROCM, 'llvm', 'lib')}",
         "-o", tmp]
     if verbose:

@@ -35,6 +35,44 @@ int fail(int code, const char *fmt, ...) {
 
 void clear_error() { g_error.clear(); }
 
+// Estimate from per-shift partial sums (max, sum exp(lp - max), dead
+// count): Section 2.1 (mean over shifts of the sample means) and Section 4
+// (standard error over the shift means, relative error).
+void estimate_from_parts(const std::vector<double> &part, int M, int64_t N, tlrqmc_result *out) {
+  std::vector<double> Ls(M);
+  double mx = -INFINITY;
+  int64_t dead = 0;
+  for (int s = 0; s < M; ++s) {
+    const double pm = part[3 * s], ps = part[3 * s + 1];
+    Ls[s] = (pm > -INFINITY && ps > 0.0) ? pm + std::log(ps) - std::log(static_cast<double>(N)) : -INFINITY;
+    mx = std::max(mx, Ls[s]);
+    dead += static_cast<int64_t>(part[3 * s + 2]);
+  }
+  out->n_dead = dead;
+  out->n_shifts = M;
+  for (int s = 0; s < 64; ++s) out->log_p_shift[s] = s < M ? Ls[s] : 0.0;
+  if (!(mx > -INFINITY)) {
+    out->log_p = -INFINITY;
+    out->p = 0.0;
+    out->std_err = 0.0;
+    out->rel_err = std::numeric_limits<double>::quiet_NaN();
+    return;
+  }
+  double mean = 0.0;
+  for (int s = 0; s < M; ++s) mean += std::exp(Ls[s] - mx);
+  mean /= M;
+  double ss = 0.0;
+  for (int s = 0; s < M; ++s) {
+    const double d = std::exp(Ls[s] - mx) - mean;
+    ss += d * d;
+  }
+  const double se = std::sqrt(ss / (static_cast<double>(M) * (M - 1)));
+  out->log_p = mx + std::log(mean);
+  out->p = std::exp(out->log_p);
+  out->std_err = se * std::exp(mx);
+  out->rel_err = se / mean;
+}
+
 namespace {
 
 // Device buffers of one estimator call, released on scope exit.
@@ -59,20 +97,6 @@ struct Scratch {
 constexpr int64_t kMultiStreamSamples = 131072;
 constexpr int kWorkerStreams = 2;
 constexpr int64_t kScratchBudget = int64_t{64} << 30;
-
-// Events created during one call, destroyed on scope exit.
-struct Events {
-  std::vector<hipEvent_t> evs;
-  ~Events() {
-    for (hipEvent_t e : evs) (void)hipEventDestroy(e);
-  }
-  hipEvent_t make() {
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    evs.push_back(e);
-    return e;
-  }
-};
 
 // HIP events around launches (on the launch's own stream), summed per
 // kernel kind.
@@ -156,41 +180,6 @@ int fail_device(tlrqmc_ctx *ctx, size_t nworkers) {
   return TLRQMC_EDEVICE;
 }
 
-void finish_estimate(const std::vector<double> &part, int M, int64_t N, tlrqmc_result *out) {
-  std::vector<double> Ls(M);
-  double mx = -INFINITY;
-  int64_t dead = 0;
-  for (int s = 0; s < M; ++s) {
-    const double pm = part[3 * s], ps = part[3 * s + 1];
-    Ls[s] = (pm > -INFINITY && ps > 0.0) ? pm + std::log(ps) - std::log(static_cast<double>(N)) : -INFINITY;
-    mx = std::max(mx, Ls[s]);
-    dead += static_cast<int64_t>(part[3 * s + 2]);
-  }
-  out->n_dead = dead;
-  out->n_shifts = M;
-  for (int s = 0; s < 64; ++s) out->log_p_shift[s] = s < M ? Ls[s] : 0.0;
-  if (!(mx > -INFINITY)) {
-    out->log_p = -INFINITY;
-    out->p = 0.0;
-    out->std_err = 0.0;
-    out->rel_err = std::numeric_limits<double>::quiet_NaN();
-    return;
-  }
-  double mean = 0.0;
-  for (int s = 0; s < M; ++s) mean += std::exp(Ls[s] - mx);
-  mean /= M;
-  double ss = 0.0;
-  for (int s = 0; s < M; ++s) {
-    const double d = std::exp(Ls[s] - mx) - mean;
-    ss += d * d;
-  }
-  const double se = std::sqrt(ss / (static_cast<double>(M) * (M - 1)));
-  out->log_p = mx + std::log(mean);
-  out->p = std::exp(out->log_p);
-  out->std_err = se * std::exp(mx);
-  out->rel_err = se / mean;
-}
-
 // Shared driver of mvn_prob, mvt_prob and tlrqmc_sample_logp.  Samples
 // g0 .. g0+count-1 of the flattened (shift, k) index space are swept; a
 // full estimate (reduce = true) needs g0 = 0 and count = N M.
@@ -231,7 +220,7 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
         part[3 * s] = -INFINITY;
         part[3 * s + 2] = static_cast<double>(N);
       }
-      finish_estimate(part, M, N, out);
+      estimate_from_parts(part, M, N, out);
     }
     return TLRQMC_OK;
   }
@@ -362,7 +351,7 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
       (void)hipStreamWaitEvent(st, e, 0);
     }
   if (reduce) {
-    ReduceParams rp{N, d_logp, d_part};
+    ReduceParams rp{N, M, d_logp, d_part};
     prof.begin(TLRQMC_KERNEL_REDUCE, st);
     launch_reduce(st, rp, M);
     prof.end(st);
@@ -379,7 +368,7 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, ev0, ev1);
     if (out) {
-      if (reduce) finish_estimate(part, M, N, out);
+      if (reduce) estimate_from_parts(part, M, N, out);
       out->seconds = ms * 1e-3;
       out->chunks = chunks;
       prof.collect(out, ev0);
@@ -408,6 +397,26 @@ int tlrqmc_ctx::worker_streams(int count) {
     workers.push_back(s);
   }
   return TLRQMC_OK;
+}
+
+double *tlrqmc_ctx::pinned(int slot, size_t bytes) {
+  if (static_cast<int>(staging.size()) <= slot) staging.resize(slot + 1, {nullptr, 0});
+  auto &b = staging[slot];
+  if (b.second < bytes) {
+    if (b.first) (void)hipHostFree(b.first);
+    b = {nullptr, 0};
+    void *p = nullptr;
+    const size_t want = bytes + bytes / 4;  // headroom against regrowth
+    if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) return nullptr;
+    b = {p, want};
+  }
+  return static_cast<double *>(b.first);
+}
+
+void tlrqmc_ctx::release_pinned() {
+  for (auto &b : staging)
+    if (b.first) (void)hipHostFree(b.first);
+  staging.clear();
 }
 
 void tlrqmc_ctx::dfree(void *p) {
@@ -447,6 +456,8 @@ void tlrqmc_ctx_destroy(tlrqmc_ctx *ctx) {
     (void)hipStreamSynchronize(s);
     (void)hipStreamDestroy(s);
   }
+  ctx->release_pinned();
+  release_blas(ctx);
   delete ctx;
 }
 
@@ -469,6 +480,7 @@ int tlrqmc_factor_stats(const tlrqmc_factor *f, tlrqmc_factor_info *o) {
   o->diag_doubles = static_cast<int64_t>(f->h_diag.size());
   o->uv_doubles = static_cast<int64_t>(f->h_U.size());
   o->device_bytes = f->device_bytes;
+  for (int k = 0; k < 4; ++k) o->setup_seconds[k] = f->setup_seconds[k];
   return TLRQMC_OK;
 }
 

@@ -34,6 +34,19 @@ __device__ __forceinline__ const TLRQMC_CONST T *as_const(const T *p) {
   return (const TLRQMC_CONST T *)p;
 }
 
+// Copy of a wave-uniform descriptor in device memory, read with scalar
+// loads (T is a plain struct of 8-byte multiples).
+template <class T>
+__device__ __forceinline__ T load_uniform(const T *p) {
+  static_assert(sizeof(T) % 8 == 0, "descriptor size");
+  T out;
+  const auto src = as_const(reinterpret_cast<const uint64_t *>(p));
+  uint64_t *dst = reinterpret_cast<uint64_t *>(&out);
+#pragma unroll
+  for (int i = 0; i < static_cast<int>(sizeof(T) / 8); ++i) dst[i] = src[i];
+  return out;
+}
+
 // The coefficient table through a pointer the optimizer cannot see through:
 // the loads stay inside the loop that calls the function (one scalar load
 // per few coefficients) instead of being hoisted, which would pin all 134

@@ -18,17 +18,6 @@ namespace tlrqmc {
 
 namespace {
 
-int upload(tlrqmc_ctx *ctx, const void *host, size_t bytes, void **dev, int64_t &total) {
-  *dev = nullptr;
-  if (bytes == 0) return TLRQMC_OK;
-  *dev = ctx->dmalloc(bytes);
-  if (!*dev) return fail(TLRQMC_ENOMEM, "device allocation of %zu bytes failed", bytes);
-  total += static_cast<int64_t>(bytes);
-  if (hipMemcpyAsync(*dev, host, bytes, hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
-    return fail(TLRQMC_EDEVICE, "hipMemcpyAsync to device failed");
-  return TLRQMC_OK;
-}
-
 // x = hi + lo with hi = bf16(float(x)), lo = bf16(float(x - hi)), both
 // rounded to nearest even.
 void split_bf16(double x, unsigned short &hi, unsigned short &lo) {
@@ -127,50 +116,25 @@ int factor_build(tlrqmc_ctx *ctx, int64_t n, int m, const int32_t *perm, const d
       }
       o += static_cast<int64_t>(mi) * mi;
     }
-    for (double v : f->h_U)
-      if (!std::isfinite(v)) return fail(TLRQMC_EINVAL, "non-finite entry in U");
-    for (double v : f->h_V)
-      if (!std::isfinite(v)) return fail(TLRQMC_EINVAL, "non-finite entry in V");
+    int bad = 0;
+    const int64_t nu = static_cast<int64_t>(f->h_U.size()), nv = static_cast<int64_t>(f->h_V.size());
+#pragma omp parallel for reduction(| : bad)
+    for (int64_t q = 0; q < nu; ++q) bad |= std::isfinite(f->h_U[q]) ? 0 : 1;
+    if (bad) return fail(TLRQMC_EINVAL, "non-finite entry in U");
+#pragma omp parallel for reduction(| : bad)
+    for (int64_t q = 0; q < nv; ++q) bad |= std::isfinite(f->h_V[q]) ? 0 : 2;
+    if (bad) return fail(TLRQMC_EINVAL, "non-finite entry in V");
   }
-  // ---- blocked diagonal tiles (row blocks of SB, see the sweep kernel)
+  // Offsets first, then every tile's layout in parallel (tiles are
+  // independent).
   constexpr int SB = kSweepBlock;
-  std::vector<double> hb;
+  std::vector<int64_t> dsrc(r + 1, 0);
   f->diag_off.assign(r + 1, 0);
-  {
-    int64_t o = 0;
-    for (int i = 0; i < r; ++i) {
-      const int mi = f->tm[i];
-      const int nb = (mi + SB - 1) / SB;
-      f->diag_off[i] = static_cast<int64_t>(hb.size());
-      hb.resize(hb.size() + static_cast<size_t>(nb) * (nb + 1) / 2 * SB * SB, 0.0);
-      double *T = hb.data() + f->diag_off[i];
-      const double *src = f->h_diag.data() + o;
-      auto Bat = [&](int t, int u) { return src[static_cast<int64_t>(t) * mi + u]; };
-      for (int q = 0; q < nb; ++q) {
-        for (int pb = 0; pb <= q; ++pb) {
-          double *blk = T + (static_cast<int64_t>(q) * (q + 1) / 2 + pb) * SB * SB;
-          if (pb < q) {
-            for (int u = 0; u < SB; ++u)
-              for (int t = 0; t < SB; ++t) {
-                const int row = SB * q + t, c = SB * pb + u;
-                blk[u * SB + t] = row < mi ? Bat(row, c) : 0.0;
-              }
-          } else {
-            for (int t = 0; t < SB; ++t) {
-              const int row = SB * q + t;
-              if (row >= mi) continue;
-              blk[t * SB] = 1.0 / Bat(row, row);
-              for (int ii = 1; t + ii < SB; ++ii)
-                if (row + ii < mi) blk[t * SB + ii] = Bat(row + ii, row);
-            }
-          }
-        }
-      }
-      o += static_cast<int64_t>(mi) * mi;
-    }
-    f->diag_off[r] = static_cast<int64_t>(hb.size());
+  for (int i = 0; i < r; ++i) {
+    const int nb = (f->tm[i] + SB - 1) / SB;
+    dsrc[i + 1] = dsrc[i] + static_cast<int64_t>(f->tm[i]) * f->tm[i];
+    f->diag_off[i + 1] = f->diag_off[i] + static_cast<int64_t>(nb) * (nb + 1) / 2 * SB * SB;
   }
-  // ---- U_row(i) column-major (rows padded to kLrRows), V_panel(j) row-major
   std::vector<int64_t> u_src(static_cast<size_t>(r) * r, 0), v_src(static_cast<size_t>(r) * r, 0);
   {
     int64_t ou = 0, ov = 0;
@@ -183,109 +147,144 @@ int factor_build(tlrqmc_ctx *ctx, int64_t n, int m, const int32_t *perm, const d
         ov += static_cast<int64_t>(f->tm[j]) * k;
       }
   }
-  std::vector<double> hu, hv;
-  std::vector<int32_t> hz;
   f->urow_off.assign(r + 1, 0);
   f->urow_ld.assign(r, 0);
-  for (int i = 0; i < r; ++i) {
-    const int lda = static_cast<int>(round_up(f->tm[i], kLrRows));
-    f->urow_ld[i] = lda;
-    f->urow_off[i] = static_cast<int64_t>(hu.size());
-    hu.resize(hu.size() + static_cast<size_t>(lda) * f->krow[i], 0.0);
-    double *dst = hu.data() + f->urow_off[i];
-    int64_t col = 0;
-    for (int j = 0; j < i; ++j) {
-      const int k = f->rank[static_cast<size_t>(i) * r + j];
-      const double *src = f->h_U.data() + u_src[static_cast<size_t>(i) * r + j];
-      for (int c = 0; c < k; ++c, ++col)
-        for (int t = 0; t < f->tm[i]; ++t) dst[col * lda + t] = src[static_cast<int64_t>(t) * k + c];
-    }
-  }
-  f->urow_off[r] = static_cast<int64_t>(hu.size());
   f->vpan_off.assign(r + 1, 0);
   f->vpan_ld.assign(r, 0);
   f->zmap_off.assign(r + 1, 0);
-  for (int j = 0; j < r; ++j) {
-    const int ldv = static_cast<int>(round_up(std::max<int64_t>(f->kcol[j], 1), kLrRows));
-    f->vpan_ld[j] = ldv;
-    f->vpan_off[j] = static_cast<int64_t>(hv.size());
-    f->zmap_off[j] = static_cast<int64_t>(hz.size());
-    hv.resize(hv.size() + static_cast<size_t>(ldv) * f->tm[j], 0.0);
-    double *dst = hv.data() + f->vpan_off[j];
-    int64_t col = 0;
-    for (int i = j + 1; i < r; ++i) {
-      const int k = f->rank[static_cast<size_t>(i) * r + j];
-      if (k == 0) continue;
-      // Z row of (i, j, c): zoff[i] + (ranks of tiles (i, 0..j-1)) + c
-      int64_t zr = f->zoff[i];
-      for (int jj = 0; jj < j; ++jj) zr += f->rank[static_cast<size_t>(i) * r + jj];
-      const double *src = f->h_V.data() + v_src[static_cast<size_t>(i) * r + j];
-      for (int c = 0; c < k; ++c, ++col) {
-        for (int t = 0; t < f->tm[j]; ++t) dst[static_cast<int64_t>(t) * ldv + col] = src[static_cast<int64_t>(t) * k + c];
-        hz.push_back(static_cast<int32_t>(zr + c));
-      }
-    }
-  }
-  f->vpan_off[r] = static_cast<int64_t>(hv.size());
-  f->zmap_off[r] = static_cast<int64_t>(hz.size());
-  // ---- precision form: BF16 hi/lo splits and the padded Z layout
   f->kp_row.assign(r, 0);
   f->zoffp.assign(r + 1, 0);
-  for (int i = 0; i < r; ++i) {
-    f->kp_row[i] = static_cast<int>(round_up(f->krow[i], 32));
-    f->zoffp[i + 1] = f->zoffp[i] + f->kp_row[i];
-  }
-  f->zp_tot = f->zoffp[r];
-  std::vector<unsigned short> hub, hvb;
-  std::vector<int32_t> hzp;
   f->ubf_off.assign(r + 1, 0);
   f->ubf_size.assign(r, 0);
-  for (int i = 0; i < r; ++i) {
-    const int64_t rows = lr_mfma_rows(f->tm[i]);
-    const int64_t kp = f->kp_row[i];
-    f->ubf_off[i] = static_cast<int64_t>(hub.size());
-    f->ubf_size[i] = rows * kp;
-    hub.resize(hub.size() + 2 * rows * kp, 0);
-    unsigned short *hi = hub.data() + f->ubf_off[i], *lo = hi + rows * kp;
-    const double *src = hu.data() + f->urow_off[i];  // column-major, lda = urow_ld[i]
-    for (int64_t col = 0; col < f->krow[i]; ++col)
-      for (int t = 0; t < f->tm[i]; ++t) split_bf16(src[col * f->urow_ld[i] + t], hi[t * kp + col], lo[t * kp + col]);
-  }
-  f->ubf_off[r] = static_cast<int64_t>(hub.size());
   f->vbf_off.assign(r + 1, 0);
   f->vbf_size.assign(r, 0);
   f->vbf_mp.assign(r, 0);
-  for (int j = 0; j < r; ++j) {
-    const int64_t kp = lr_mfma_rows(static_cast<int>(f->kcol[j]));
-    const int64_t mp = round_up(f->tm[j], 32);
-    f->vbf_mp[j] = static_cast<int>(mp);
-    f->vbf_off[j] = static_cast<int64_t>(hvb.size());
-    f->vbf_size[j] = kp * mp;
-    hvb.resize(hvb.size() + 2 * kp * mp, 0);
-    unsigned short *hi = hvb.data() + f->vbf_off[j], *lo = hi + kp * mp;
-    const double *src = hv.data() + f->vpan_off[j];  // row-major, ldv = vpan_ld[j]
-    for (int64_t col = 0; col < f->kcol[j]; ++col) {
-      for (int t = 0; t < f->tm[j]; ++t) split_bf16(src[static_cast<int64_t>(t) * f->vpan_ld[j] + col], hi[col * mp + t], lo[col * mp + t]);
-      // padded Z row of the same (i, j, c) as the unpadded zmap entry
-      const int32_t zr = hz[f->zmap_off[j] + col];
-      int i = 0;
-      while (f->zoff[i + 1] <= zr) ++i;
-      hzp.push_back(static_cast<int32_t>(f->zoffp[i] + (zr - f->zoff[i])));
+  for (int i = 0; i < r; ++i) {
+    f->urow_ld[i] = static_cast<int>(round_up(f->tm[i], kLrRows));
+    f->urow_off[i + 1] = f->urow_off[i] + static_cast<int64_t>(f->urow_ld[i]) * f->krow[i];
+    f->vpan_ld[i] = static_cast<int>(round_up(std::max<int64_t>(f->kcol[i], 1), kLrRows));
+    f->vpan_off[i + 1] = f->vpan_off[i] + static_cast<int64_t>(f->vpan_ld[i]) * f->tm[i];
+    f->zmap_off[i + 1] = f->zmap_off[i] + f->kcol[i];
+    // precision form: BF16 hi/lo splits and a Z layout with row blocks padded to 32
+    f->kp_row[i] = static_cast<int>(round_up(f->krow[i], 32));
+    f->zoffp[i + 1] = f->zoffp[i] + f->kp_row[i];
+    f->ubf_size[i] = lr_mfma_rows(f->tm[i]) * f->kp_row[i];
+    f->ubf_off[i + 1] = f->ubf_off[i] + 2 * f->ubf_size[i];
+    f->vbf_mp[i] = static_cast<int>(round_up(f->tm[i], 32));
+    f->vbf_size[i] = lr_mfma_rows(static_cast<int>(f->kcol[i])) * f->vbf_mp[i];
+    f->vbf_off[i + 1] = f->vbf_off[i] + 2 * f->vbf_size[i];
+  }
+  f->zp_tot = f->zoffp[r];
+  // Every device array is laid out directly in one pinned staging buffer
+  // (already mapped, so no page faults), cleared in parallel, filled tile by
+  // tile, then uploaded.
+  const std::vector<uint64_t> gen = richtmyer_generators(n + 1);
+  const size_t sizes[8] = {static_cast<size_t>(f->diag_off[r]) * 8, static_cast<size_t>(f->urow_off[r]) * 8,
+                           static_cast<size_t>(f->vpan_off[r]) * 8, static_cast<size_t>(f->zmap_off[r]) * 4,
+                           gen.size() * 8, static_cast<size_t>(f->ubf_off[r]) * 2,
+                           static_cast<size_t>(f->vbf_off[r]) * 2, static_cast<size_t>(f->zmap_off[r]) * 4};
+  size_t offs[9] = {0};
+  for (int k = 0; k < 8; ++k) offs[k + 1] = offs[k] + static_cast<size_t>(round_up(static_cast<int64_t>(sizes[k]), 256));
+  char *stage = reinterpret_cast<char *>(ctx->pinned(2, offs[8]));
+  if (!stage) return fail(TLRQMC_ENOMEM, "pinned host staging allocation failed");
+  {
+    const int64_t words = static_cast<int64_t>(offs[8] / 8);
+    uint64_t *w = reinterpret_cast<uint64_t *>(stage);
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < words; ++q) w[q] = 0;
+  }
+  double *hb = reinterpret_cast<double *>(stage + offs[0]);
+  double *hu = reinterpret_cast<double *>(stage + offs[1]);
+  double *hv = reinterpret_cast<double *>(stage + offs[2]);
+  int32_t *hz = reinterpret_cast<int32_t *>(stage + offs[3]);
+  std::memcpy(stage + offs[4], gen.data(), sizes[4]);
+  unsigned short *hub = reinterpret_cast<unsigned short *>(stage + offs[5]);
+  unsigned short *hvb = reinterpret_cast<unsigned short *>(stage + offs[6]);
+  int32_t *hzp = reinterpret_cast<int32_t *>(stage + offs[7]);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int i = 0; i < r; ++i) {
+    // blocked diagonal tile (row blocks of SB, see the sweep kernel)
+    const int mi = f->tm[i];
+    const int nb = (mi + SB - 1) / SB;
+    double *T = hb + f->diag_off[i];
+    const double *src = f->h_diag.data() + dsrc[i];
+    auto Bat = [&](int t, int u) { return src[static_cast<int64_t>(t) * mi + u]; };
+    for (int q = 0; q < nb; ++q)
+      for (int pb = 0; pb <= q; ++pb) {
+        double *blk = T + (static_cast<int64_t>(q) * (q + 1) / 2 + pb) * SB * SB;
+        if (pb < q) {
+          for (int u = 0; u < SB; ++u)
+            for (int t = 0; t < SB; ++t) {
+              const int row = SB * q + t, c = SB * pb + u;
+              blk[u * SB + t] = row < mi ? Bat(row, c) : 0.0;
+            }
+        } else {
+          for (int t = 0; t < SB; ++t) {
+            const int row = SB * q + t;
+            if (row >= mi) continue;
+            blk[t * SB] = 1.0 / Bat(row, row);
+            for (int ii = 1; t + ii < SB; ++ii)
+              if (row + ii < mi) blk[t * SB + ii] = Bat(row + ii, row);
+          }
+        }
+      }
+    // U_row(i): column-major, rows padded to kLrRows; its BF16 split
+    // row-major with k padded to 32
+    const int lda = f->urow_ld[i];
+    double *du = hu + f->urow_off[i];
+    const int64_t kp = f->kp_row[i];
+    unsigned short *hi = hub + f->ubf_off[i], *lo = hi + f->ubf_size[i];
+    int64_t col = 0;
+    for (int j = 0; j < i; ++j) {
+      const int k = f->rank[static_cast<size_t>(i) * r + j];
+      const double *su = f->h_U.data() + u_src[static_cast<size_t>(i) * r + j];
+      for (int c = 0; c < k; ++c, ++col)
+        for (int t = 0; t < mi; ++t) {
+          const double x = su[static_cast<int64_t>(t) * k + c];
+          du[col * lda + t] = x;
+          split_bf16(x, hi[t * kp + col], lo[t * kp + col]);
+        }
+    }
+    // V_panel(i): row-major, columns padded to kLrRows; zmap sends column c
+    // of tile (l, i) to Z row zoff[l] + (ranks of tiles (l, 0..i-1)) + c;
+    // the BF16 split of V_panel^T is row-major with t padded to 32
+    const int ldv = f->vpan_ld[i];
+    double *dv = hv + f->vpan_off[i];
+    int32_t *z = hz + f->zmap_off[i], *zp = hzp + f->zmap_off[i];
+    const int64_t mp = f->vbf_mp[i];
+    unsigned short *vhi = hvb + f->vbf_off[i], *vlo = vhi + f->vbf_size[i];
+    col = 0;
+    for (int l = i + 1; l < r; ++l) {
+      const int k = f->rank[static_cast<size_t>(l) * r + i];
+      if (k == 0) continue;
+      int64_t zr = f->zoff[l];
+      for (int jj = 0; jj < i; ++jj) zr += f->rank[static_cast<size_t>(l) * r + jj];
+      const double *sv = f->h_V.data() + v_src[static_cast<size_t>(l) * r + i];
+      for (int c = 0; c < k; ++c, ++col) {
+        for (int t = 0; t < mi; ++t) {
+          const double x = sv[static_cast<int64_t>(t) * k + c];
+          dv[static_cast<int64_t>(t) * ldv + col] = x;
+          split_bf16(x, vhi[col * mp + t], vlo[col * mp + t]);
+        }
+        z[col] = static_cast<int32_t>(zr + c);
+        zp[col] = static_cast<int32_t>(f->zoffp[l] + (zr + c - f->zoff[l]));
+      }
     }
   }
-  f->vbf_off[r] = static_cast<int64_t>(hvb.size());
-  // lattice generators A_0..A_n
-  const std::vector<uint64_t> gen = richtmyer_generators(n + 1);
+  void **dst[8] = {reinterpret_cast<void **>(&f->d_diag), reinterpret_cast<void **>(&f->d_urow),
+                   reinterpret_cast<void **>(&f->d_vpan), reinterpret_cast<void **>(&f->d_zmap),
+                   reinterpret_cast<void **>(&f->d_gen),  reinterpret_cast<void **>(&f->d_ubf),
+                   reinterpret_cast<void **>(&f->d_vbf),  reinterpret_cast<void **>(&f->d_zmapp)};
   int64_t total = 0;
-  int st;
-  if ((st = upload(ctx, hb.data(), hb.size() * sizeof(double), reinterpret_cast<void **>(&f->d_diag), total))) return st;
-  if ((st = upload(ctx, hu.data(), hu.size() * sizeof(double), reinterpret_cast<void **>(&f->d_urow), total))) return st;
-  if ((st = upload(ctx, hv.data(), hv.size() * sizeof(double), reinterpret_cast<void **>(&f->d_vpan), total))) return st;
-  if ((st = upload(ctx, hz.data(), hz.size() * sizeof(int32_t), reinterpret_cast<void **>(&f->d_zmap), total))) return st;
-  if ((st = upload(ctx, gen.data(), gen.size() * sizeof(uint64_t), reinterpret_cast<void **>(&f->d_gen), total))) return st;
-  if ((st = upload(ctx, hub.data(), hub.size() * 2, reinterpret_cast<void **>(&f->d_ubf), total))) return st;
-  if ((st = upload(ctx, hvb.data(), hvb.size() * 2, reinterpret_cast<void **>(&f->d_vbf), total))) return st;
-  if ((st = upload(ctx, hzp.data(), hzp.size() * 4, reinterpret_cast<void **>(&f->d_zmapp), total))) return st;
+  for (int k = 0; k < 8; ++k) {
+    *dst[k] = nullptr;
+    if (sizes[k] == 0) continue;
+    *dst[k] = ctx->dmalloc(sizes[k]);
+    if (!*dst[k]) return fail(TLRQMC_ENOMEM, "device allocation of %zu bytes failed", sizes[k]);
+    total += static_cast<int64_t>(sizes[k]);
+    if (hipMemcpyAsync(*dst[k], stage + offs[k], sizes[k], hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
+      return fail(TLRQMC_EDEVICE, "hipMemcpyAsync to device failed");
+  }
   if (hipStreamSynchronize(ctx->stream) != hipSuccess) return fail(TLRQMC_EDEVICE, "stream synchronize failed");
   f->device_bytes = total;
   *out = guard.release();

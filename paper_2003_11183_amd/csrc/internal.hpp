@@ -15,6 +15,10 @@ namespace tlrqmc {
 int fail(int code, const char *fmt, ...);
 void clear_error();
 
+// Estimate from per-shift partial sums (max, sum of exp(log P - max), count
+// of empty samples), as the device reduction writes them.
+void estimate_from_parts(const std::vector<double> &part, int M, int64_t N, tlrqmc_result *out);
+
 // Row-block height of the diagonal-tile sweep and the padded row count of a
 // tile in the blocked layout.
 constexpr int kSweepBlock = 16;
@@ -22,6 +26,20 @@ constexpr int kSweepBlock = 16;
 constexpr int kLrRows = 64;
 
 inline int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
+
+// Events created during one call, destroyed on scope exit.
+struct Events {
+  std::vector<hipEvent_t> evs;
+  ~Events() {
+    for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+  }
+  hipEvent_t make() {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    evs.push_back(e);
+    return e;
+  }
+};
 
 }  // namespace tlrqmc
 
@@ -34,9 +52,14 @@ struct tlrqmc_ctx {
   // run concurrently, so that the last partial round of waves of one
   // chunk's launch is filled by another chunk's work.
   std::vector<hipStream_t> workers;
+  // Pinned host staging buffers (factor download), kept between calls.
+  std::vector<std::pair<void *, size_t>> staging;
+  void *blas = nullptr;  // rocblas_handle, created by the first factor build
   void *dmalloc(size_t bytes);
   void dfree(void *p);
   int worker_streams(int count);
+  double *pinned(int slot, size_t bytes);
+  void release_pinned();
 };
 
 // Device-resident TLR factor.  Host vectors keep the exchange layout for
@@ -84,9 +107,13 @@ struct tlrqmc_factor {
   std::vector<int64_t> zoffp;    // first padded Z row of tile i
   int64_t zp_tot = 0;
   int64_t device_bytes = 0;
+  double setup_seconds[4] = {0, 0, 0, 0};  // tlr_factor phases
 };
 
 namespace tlrqmc {
+
+// Destroy a context's cached rocBLAS handle (setup.cpp).
+void release_blas(tlrqmc_ctx *ctx);
 
 // ---- host lattice (lattice.cpp) ----
 std::vector<uint64_t> richtmyer_generators(int64_t dim);
@@ -132,6 +159,7 @@ struct LrParams {
 
 struct ReduceParams {
   int64_t N;
+  int M;                   // shifts (blocks), read by the batched launch
   const double *logp;
   double *part;            // per shift: max, sum exp(lp - max), dead count
 };
@@ -159,5 +187,16 @@ void launch_sweep(hipStream_t s, const SweepParams &p, bool two_sided, bool scal
 void launch_delta_f64(hipStream_t s, const LrParams &p);
 void launch_zproj_f64(hipStream_t s, const LrParams &p);
 void launch_reduce(hipStream_t s, const ReduceParams &p, int n_shifts);
+
+// Batched launches: d points to n descriptors in device memory; slot i's
+// launch is the one its descriptor would make alone.
+void launch_init_batch(hipStream_t s, const InitParams *d, int n, int64_t max_count);
+void launch_sweep_batch(hipStream_t s, const SweepParams *d, int n, int64_t max_count, bool two_sided, bool scaled,
+                        bool mixed);
+void launch_delta_f64_batch(hipStream_t s, const LrParams *d, int n, int64_t max_count, int max_rows);
+void launch_zproj_f64_batch(hipStream_t s, const LrParams *d, int n, int64_t max_count, int max_rows);
+void launch_reduce_batch(hipStream_t s, const ReduceParams *d, int n, int max_shifts);
+void launch_lr_mfma_batch(hipStream_t s, const MfmaLrParams *d, int n, int rt, bool fp64_b, bool map,
+                          int64_t max_blocks);
 
 }  // namespace tlrqmc

@@ -25,8 +25,7 @@ __device__ __forceinline__ double lattice_point(uint64_t k, uint64_t A, uint64_t
 }
 
 // ---------------------------------------------------------------- init ----
-__global__ __launch_bounds__(256) void k_init(InitParams p) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+__device__ __forceinline__ void init_body(const InitParams &p, int64_t i) {
   if (i >= p.count) return;
   const int64_t g = p.g0 + i;
   p.logp[i] = 0.0;
@@ -36,6 +35,17 @@ __global__ __launch_bounds__(256) void k_init(InitParams p) {
     const double w0 = lattice_point(k, p.A[0], p.D[s * p.ldD]);
     p.R[i] = chi_inv(p.nu, w0) / sqrt(p.nu);
   }
+}
+
+__global__ __launch_bounds__(256) void k_init(InitParams p) {
+  init_body(p, static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x);
+}
+
+// Batched launches (continuous batching of requests): one descriptor per
+// slot, slot = blockIdx.y; the descriptor is read with scalar loads.
+__global__ __launch_bounds__(256) void k_init_batch(const InitParams *ps) {
+  const InitParams p = load_uniform(ps + blockIdx.y);
+  init_body(p, static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x);
 }
 
 // --------------------------------------------------------------- sweep ----
@@ -51,9 +61,8 @@ __global__ __launch_bounds__(256) void k_init(InitParams p) {
 // diagonal is added and the window slides down by one, so every index into
 // acc is a compile-time constant and acc stays in registers.
 template <bool TWO_SIDED, bool SCALED, bool MIXED>
-__global__ __launch_bounds__(256) void k_sweep(SweepParams p) {
+__device__ __forceinline__ void sweep_body(const SweepParams &p, int64_t si) {
   constexpr int SB = kSweepBlock;
-  const int64_t si = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   if (si >= p.count) return;
   const int64_t g = p.g0 + si;
   const int64_t s = g / p.N;
@@ -119,13 +128,22 @@ __global__ __launch_bounds__(256) void k_sweep(SweepParams p) {
   p.logp[si] = lp;
 }
 
+template <bool TWO_SIDED, bool SCALED, bool MIXED>
+__global__ __launch_bounds__(256) void k_sweep(SweepParams p) {
+  sweep_body<TWO_SIDED, SCALED, MIXED>(p, static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x);
+}
+
+template <bool TWO_SIDED, bool SCALED, bool MIXED>
+__global__ __launch_bounds__(256) void k_sweep_batch(const SweepParams *ps) {
+  const SweepParams p = load_uniform(ps + blockIdx.y);
+  sweep_body<TWO_SIDED, SCALED, MIXED>(p, static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x);
+}
+
 // ------------------------------------------------------- low rank, FP64 ----
 // Delta(t, s) = sum_q U_row(t, q) Z(q, s) for 64 rows t per block row.
 // U_row is column-major with leading dimension lda (rows padded with zeros).
-__global__ __launch_bounds__(256) void k_delta_f64(LrParams p) {
-  const int64_t si = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (si >= p.count) return;
-  const int t0 = blockIdx.y * kLrRows;
+__device__ __forceinline__ void delta_f64_body(const LrParams &p, int64_t si, int t0) {
+  if (si >= p.count || t0 >= p.rows) return;
   double acc[kLrRows];
 #pragma unroll
   for (int t = 0; t < kLrRows; ++t) acc[t] = 0.0;
@@ -145,12 +163,19 @@ __global__ __launch_bounds__(256) void k_delta_f64(LrParams p) {
     if (t < nr) O[static_cast<int64_t>(t0 + t) * p.ld] = acc[t];
 }
 
+__global__ __launch_bounds__(256) void k_delta_f64(LrParams p) {
+  delta_f64_body(p, static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x, blockIdx.y * kLrRows);
+}
+
+__global__ __launch_bounds__(256) void k_delta_f64_batch(const LrParams *ps) {
+  const LrParams p = load_uniform(ps + blockIdx.z);
+  delta_f64_body(p, static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x, blockIdx.y * kLrRows);
+}
+
 // Z(map(c), s) = sum_t V_panel(t, c) Y(t, s) for 64 columns c per block row.
 // V_panel is row-major with leading dimension lda (columns padded with zeros).
-__global__ __launch_bounds__(256) void k_zproj_f64(LrParams p) {
-  const int64_t si = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (si >= p.count) return;
-  const int c0 = blockIdx.y * kLrRows;
+__device__ __forceinline__ void zproj_f64_body(const LrParams &p, int64_t si, int c0) {
+  if (si >= p.count || c0 >= p.rows) return;
   double acc[kLrRows];
 #pragma unroll
   for (int c = 0; c < kLrRows; ++c) acc[c] = 0.0;
@@ -171,14 +196,20 @@ __global__ __launch_bounds__(256) void k_zproj_f64(LrParams p) {
     if (c < nc) O[static_cast<int64_t>(map[c0 + c]) * p.ld] = acc[c];
 }
 
+__global__ __launch_bounds__(256) void k_zproj_f64(LrParams p) {
+  zproj_f64_body(p, static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x, blockIdx.y * kLrRows);
+}
+
+__global__ __launch_bounds__(256) void k_zproj_f64_batch(const LrParams *ps) {
+  const LrParams p = load_uniform(ps + blockIdx.z);
+  zproj_f64_body(p, static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x, blockIdx.y * kLrRows);
+}
+
 // -------------------------------------------------------------- reduce ----
 // One block per shift: max of log P, then sum of exp(log P - max) and the
 // count of empty samples, each lane striding in a fixed order and the lanes
 // combined by a fixed tree, so the result does not depend on scheduling.
-__global__ __launch_bounds__(256) void k_reduce(ReduceParams p) {
-  __shared__ double sh[256];
-  __shared__ double sd[256];
-  const int s = blockIdx.x;
+__device__ __forceinline__ void reduce_body(const ReduceParams &p, int s, double *sh, double *sd) {
   const int t = threadIdx.x;
   const double *lp = p.logp + static_cast<int64_t>(s) * p.N;
   double mx = -INFINITY;
@@ -218,6 +249,22 @@ __global__ __launch_bounds__(256) void k_reduce(ReduceParams p) {
   }
 }
 
+__global__ __launch_bounds__(256) void k_reduce(ReduceParams p) {
+  __shared__ double sh[256];
+  __shared__ double sd[256];
+  reduce_body(p, blockIdx.x, sh, sd);
+}
+
+// One block per (shift, request); blocks past a request's shift count
+// leave at once (the whole block takes the same branch).
+__global__ __launch_bounds__(256) void k_reduce_batch(const ReduceParams *ps) {
+  __shared__ double sh[256];
+  __shared__ double sd[256];
+  const ReduceParams p = load_uniform(ps + blockIdx.y);
+  if (static_cast<int>(blockIdx.x) >= p.M) return;
+  reduce_body(p, blockIdx.x, sh, sd);
+}
+
 // ------------------------------------------------------------ launchers ----
 static inline unsigned grid_of(int64_t count) { return static_cast<unsigned>((count + 255) / 256); }
 
@@ -251,6 +298,39 @@ void launch_zproj_f64(hipStream_t s, const LrParams &p) {
 
 void launch_reduce(hipStream_t s, const ReduceParams &p, int n_shifts) {
   hipLaunchKernelGGL(k_reduce, dim3(n_shifts), dim3(256), 0, s, p);
+}
+
+void launch_init_batch(hipStream_t s, const InitParams *d, int n, int64_t max_count) {
+  hipLaunchKernelGGL(k_init_batch, dim3(grid_of(max_count), n), dim3(256), 0, s, d);
+}
+
+void launch_sweep_batch(hipStream_t s, const SweepParams *d, int n, int64_t max_count, bool two_sided, bool scaled,
+                        bool mixed) {
+  const dim3 grid(grid_of(max_count), n), block(256);
+  if (two_sided) {
+    if (scaled) hipLaunchKernelGGL((k_sweep_batch<true, true, false>), grid, block, 0, s, d);
+    else hipLaunchKernelGGL((k_sweep_batch<true, false, false>), grid, block, 0, s, d);
+  } else if (mixed) {
+    if (scaled) hipLaunchKernelGGL((k_sweep_batch<false, true, true>), grid, block, 0, s, d);
+    else hipLaunchKernelGGL((k_sweep_batch<false, false, true>), grid, block, 0, s, d);
+  } else {
+    if (scaled) hipLaunchKernelGGL((k_sweep_batch<false, true, false>), grid, block, 0, s, d);
+    else hipLaunchKernelGGL((k_sweep_batch<false, false, false>), grid, block, 0, s, d);
+  }
+}
+
+void launch_delta_f64_batch(hipStream_t s, const LrParams *d, int n, int64_t max_count, int max_rows) {
+  const dim3 grid(grid_of(max_count), static_cast<unsigned>((max_rows + kLrRows - 1) / kLrRows), n);
+  hipLaunchKernelGGL(k_delta_f64_batch, grid, dim3(256), 0, s, d);
+}
+
+void launch_zproj_f64_batch(hipStream_t s, const LrParams *d, int n, int64_t max_count, int max_rows) {
+  const dim3 grid(grid_of(max_count), static_cast<unsigned>((max_rows + kLrRows - 1) / kLrRows), n);
+  hipLaunchKernelGGL(k_zproj_f64_batch, grid, dim3(256), 0, s, d);
+}
+
+void launch_reduce_batch(hipStream_t s, const ReduceParams *d, int n, int max_shifts) {
+  hipLaunchKernelGGL(k_reduce_batch, dim3(max_shifts, n), dim3(256), 0, s, d);
 }
 
 }  // namespace tlrqmc

@@ -16,6 +16,7 @@
 // and receives C[4 (l / 16) + i][l % 16], i = 0..3.
 #include <type_traits>
 
+#include "device_math.hpp"
 #include "internal.hpp"
 
 namespace tlrqmc {
@@ -63,11 +64,12 @@ __device__ __forceinline__ f32x4 mfma3(u16x8 ah, u16x8 al, u16x8 bh, u16x8 bl, f
 // block) pairs, row block fastest: the row blocks that share one sample
 // block's B run back to back on one XCD and re-read B from its L2.
 template <int RT, bool BD, bool MAP>
-__global__ __launch_bounds__(256) void k_lr_mfma(MfmaLrParams p, int nrb) {
+__device__ __forceinline__ void lr_mfma_body(const MfmaLrParams &p, unsigned bid, unsigned total) {
   __shared__ u16x8 Bs[2][2][4][64];  // [buffer][hi, lo][sample tile][lane]
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const unsigned total = gridDim.x, q = total / 8, rm = total % 8;
-  const unsigned xcd = blockIdx.x % 8, idx = blockIdx.x / 8;
+  const int nrb = (p.rows + 64 * RT - 1) / (64 * RT);
+  const unsigned q = total / 8, rm = total % 8;
+  const unsigned xcd = bid % 8, idx = bid / 8;
   const unsigned logical = xcd * q + min(xcd, rm) + idx;
   const unsigned rb = logical % static_cast<unsigned>(nrb), sb = logical / static_cast<unsigned>(nrb);
   const int64_t s0 = static_cast<int64_t>(sb) * 64;
@@ -136,6 +138,22 @@ __global__ __launch_bounds__(256) void k_lr_mfma(MfmaLrParams p, int nrb) {
     }
 }
 
+template <int RT, bool BD, bool MAP>
+__global__ __launch_bounds__(256) void k_lr_mfma(MfmaLrParams p) {
+  lr_mfma_body<RT, BD, MAP>(p, blockIdx.x, gridDim.x);
+}
+
+// Batched: slot = blockIdx.y; gridDim.x is a multiple of 8, so blockIdx.x
+// mod 8 is still the XCD of the work-group.
+template <int RT, bool BD, bool MAP>
+__global__ __launch_bounds__(256) void k_lr_mfma_batch(const MfmaLrParams *ps) {
+  const MfmaLrParams p = dev::load_uniform(ps + blockIdx.y);
+  const unsigned total =
+      static_cast<unsigned>((p.count + 63) / 64) * static_cast<unsigned>((p.rows + 64 * RT - 1) / (64 * RT));
+  if (blockIdx.x >= total) return;
+  lr_mfma_body<RT, BD, MAP>(p, blockIdx.x, total);
+}
+
 // Row tiles of 16 per wave: 1 or 2 for short operands, else 4 unless 2
 // pads less.
 int lr_mfma_rt(int rows) {
@@ -149,13 +167,24 @@ int64_t lr_mfma_rows(int rows) { return round_up(rows > 0 ? rows : 1, 64 * lr_mf
 namespace {
 
 template <int RT>
-void launch_rt(hipStream_t s, const MfmaLrParams &p, dim3 grid, int nrb) {
+void launch_rt(hipStream_t s, const MfmaLrParams &p, dim3 grid) {
   if (p.Bd) {
-    if (p.map) hipLaunchKernelGGL((k_lr_mfma<RT, true, true>), grid, dim3(256), 0, s, p, nrb);
-    else hipLaunchKernelGGL((k_lr_mfma<RT, true, false>), grid, dim3(256), 0, s, p, nrb);
+    if (p.map) hipLaunchKernelGGL((k_lr_mfma<RT, true, true>), grid, dim3(256), 0, s, p);
+    else hipLaunchKernelGGL((k_lr_mfma<RT, true, false>), grid, dim3(256), 0, s, p);
   } else {
-    if (p.map) hipLaunchKernelGGL((k_lr_mfma<RT, false, true>), grid, dim3(256), 0, s, p, nrb);
-    else hipLaunchKernelGGL((k_lr_mfma<RT, false, false>), grid, dim3(256), 0, s, p, nrb);
+    if (p.map) hipLaunchKernelGGL((k_lr_mfma<RT, false, true>), grid, dim3(256), 0, s, p);
+    else hipLaunchKernelGGL((k_lr_mfma<RT, false, false>), grid, dim3(256), 0, s, p);
+  }
+}
+
+template <int RT>
+void launch_batch_rt(hipStream_t s, const MfmaLrParams *d, dim3 grid, bool bd, bool map) {
+  if (bd) {
+    if (map) hipLaunchKernelGGL((k_lr_mfma_batch<RT, true, true>), grid, dim3(256), 0, s, d);
+    else hipLaunchKernelGGL((k_lr_mfma_batch<RT, true, false>), grid, dim3(256), 0, s, d);
+  } else {
+    if (map) hipLaunchKernelGGL((k_lr_mfma_batch<RT, false, true>), grid, dim3(256), 0, s, d);
+    else hipLaunchKernelGGL((k_lr_mfma_batch<RT, false, false>), grid, dim3(256), 0, s, d);
   }
 }
 
@@ -166,9 +195,19 @@ void launch_lr_mfma(hipStream_t s, const MfmaLrParams &p) {
   const int64_t nsb = (p.count + 63) / 64;
   const int nrb = (p.rows + 64 * rt - 1) / (64 * rt);
   const dim3 grid(static_cast<unsigned>(nsb * nrb));
-  if (rt == 1) launch_rt<1>(s, p, grid, nrb);
-  else if (rt == 2) launch_rt<2>(s, p, grid, nrb);
-  else launch_rt<4>(s, p, grid, nrb);
+  if (rt == 1) launch_rt<1>(s, p, grid);
+  else if (rt == 2) launch_rt<2>(s, p, grid);
+  else launch_rt<4>(s, p, grid);
+}
+
+// Every descriptor of one batched launch must have lr_mfma_rt(rows) == rt
+// and the same B type and map use; max_blocks bounds their block counts.
+void launch_lr_mfma_batch(hipStream_t s, const MfmaLrParams *d, int n, int rt, bool fp64_b, bool map,
+                          int64_t max_blocks) {
+  const dim3 grid(static_cast<unsigned>(round_up(max_blocks, 8)), static_cast<unsigned>(n));
+  if (rt == 1) launch_batch_rt<1>(s, d, grid, fp64_b, map);
+  else if (rt == 2) launch_batch_rt<2>(s, d, grid, fp64_b, map);
+  else launch_batch_rt<4>(s, d, grid, fp64_b, map);
 }
 
 }  // namespace tlrqmc

@@ -14,8 +14,10 @@
 //   Golub 1965) down to a residual far below tol, then a one-sided Jacobi
 //   SVD (Hestenes 1958) of the small triangular factor.
 #include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -284,26 +286,12 @@ int compress_tile(const double *T, int64_t ldt, int mi, int mj, double tol, int 
   return k;
 }
 
-// Host Cholesky of an nb x nb column-major block in place; returns the
-// first failing column or -1.
-int host_potrf(double *A, int nb, int lda) {
-  for (int j = 0; j < nb; ++j) {
-    double d = A[static_cast<size_t>(j) * lda + j];
-    for (int k = 0; k < j; ++k) d -= A[static_cast<size_t>(k) * lda + j] * A[static_cast<size_t>(k) * lda + j];
-    if (!(d > 0.0)) return j;
-    d = std::sqrt(d);
-    A[static_cast<size_t>(j) * lda + j] = d;
-    for (int i = j + 1; i < nb; ++i) {
-      double s = A[static_cast<size_t>(j) * lda + i];
-      for (int k = 0; k < j; ++k) s -= A[static_cast<size_t>(k) * lda + i] * A[static_cast<size_t>(k) * lda + j];
-      A[static_cast<size_t>(j) * lda + i] = s / d;
-    }
-    for (int k = j + 1; k < nb; ++k) A[static_cast<size_t>(k) * lda + j] = 0.0;
-  }
-  return -1;
-}
-
 }  // namespace
+
+void release_blas(tlrqmc_ctx *ctx) {
+  if (ctx->blas) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(ctx->blas));
+  ctx->blas = nullptr;
+}
 
 // Kernel building the permuted covariance (kernels_setup.hip).
 void launch_cov_exp(hipStream_t s, int64_t n, const double *xy_perm, double range, double variance,
@@ -394,6 +382,10 @@ int tlr_factor(tlrqmc_ctx *ctx, int64_t n, const tlrqmc_cov *cov, const int32_t 
   } else {
     std::iota(p.begin(), p.end(), 0);
   }
+  using clk = std::chrono::steady_clock;
+  auto secs = [](clk::time_point a, clk::time_point b) { return std::chrono::duration<double>(b - a).count(); };
+  double phase[4] = {0, 0, 0, 0};
+  const auto t_begin = clk::now();
   hipStream_t s = ctx->stream;
   const int64_t lda = round_up(n, 64);
   double *A = static_cast<double *>(ctx->dmalloc(static_cast<size_t>(lda) * n * sizeof(double)));
@@ -422,75 +414,101 @@ int tlr_factor(tlrqmc_ctx *ctx, int64_t n, const tlrqmc_cov *cov, const int32_t 
         return fail(TLRQMC_EDEVICE, "copy of the covariance failed");
     }
   }
-  // blocked right-looking Cholesky
-  rocblas_handle h;
-  if (rocblas_create_handle(&h) != rocblas_status_success) return fail(TLRQMC_EDEVICE, "rocblas_create_handle failed");
-  std::unique_ptr<_rocblas_handle, rocblas_status (*)(rocblas_handle)> hguard(h, rocblas_destroy_handle);
-  rocblas_set_stream(h, s);
-  const int nb = 256;
-  std::vector<double> blk(static_cast<size_t>(nb) * nb);
-  for (int64_t k0 = 0; k0 < n; k0 += nb) {
-    const int kb = static_cast<int>(std::min<int64_t>(nb, n - k0));
-    double *Akk = A + k0 * lda + k0;
-    if (hipMemcpy2DAsync(blk.data(), kb * sizeof(double), Akk, lda * sizeof(double), kb * sizeof(double), kb,
-                         hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return fail(TLRQMC_EDEVICE, "copy of a diagonal block failed");
-    const int bad = host_potrf(blk.data(), kb, kb);
-    if (bad >= 0)
-      return fail(TLRQMC_ENOTSPD, "covariance not positive definite at column %lld (tile %lld)",
-                  static_cast<long long>(k0 + bad), static_cast<long long>((k0 + bad) / m));
-    if (hipMemcpy2DAsync(Akk, lda * sizeof(double), blk.data(), kb * sizeof(double), kb * sizeof(double), kb,
-                         hipMemcpyHostToDevice, s) != hipSuccess)
-      return fail(TLRQMC_EDEVICE, "copy of a diagonal block failed");
-    const int64_t rest = n - k0 - kb;
-    if (rest > 0) {
-      const double one = 1.0, minus = -1.0;
-      double *P = A + k0 * lda + k0 + kb;
-      if (rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
-                        rocblas_diagonal_non_unit, static_cast<rocblas_int>(rest), kb, &one, Akk,
-                        static_cast<rocblas_int>(lda), P, static_cast<rocblas_int>(lda)) != rocblas_status_success ||
-          rocblas_dsyrk(h, rocblas_fill_lower, rocblas_operation_none, static_cast<rocblas_int>(rest), kb, &minus, P,
-                        static_cast<rocblas_int>(lda), &one, A + (k0 + kb) * lda + k0 + kb,
-                        static_cast<rocblas_int>(lda)) != rocblas_status_success)
-        return fail(TLRQMC_EDEVICE, "rocBLAS update failed");
-    }
+  // dense Cholesky on the device (lower triangle)
+  if (!ctx->blas) {
+    rocblas_handle nh;
+    if (rocblas_create_handle(&nh) != rocblas_status_success) return fail(TLRQMC_EDEVICE, "rocblas_create_handle failed");
+    ctx->blas = nh;
   }
-  if (hipStreamSynchronize(s) != hipSuccess) return fail(TLRQMC_EDEVICE, "Cholesky failed on the device");
-  // tiles to the exchange layout, compressing the off-diagonal ones
+  rocblas_handle h = static_cast<rocblas_handle>(ctx->blas);
+  rocblas_set_stream(h, s);
+  {
+    rocblas_int *dinfo = static_cast<rocblas_int *>(ctx->dmalloc(sizeof(rocblas_int)));
+    if (!dinfo) return fail(TLRQMC_ENOMEM, "device allocation failed");
+    std::unique_ptr<rocblas_int, std::function<void(rocblas_int *)>> iguard(dinfo, [ctx](rocblas_int *q) { ctx->dfree(q); });
+    rocblas_int info = 0;
+    if (rocsolver_dpotrf(h, rocblas_fill_lower, static_cast<rocblas_int>(n), A, static_cast<rocblas_int>(lda), dinfo) !=
+            rocblas_status_success ||
+        hipMemcpyAsync(&info, dinfo, sizeof info, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail(TLRQMC_EDEVICE, "Cholesky failed on the device");
+    if (info > 0)
+      return fail(TLRQMC_ENOTSPD, "covariance not positive definite at column %lld (tile %lld)",
+                  static_cast<long long>(info - 1), static_cast<long long>((info - 1) / m));
+  }
+  phase[0] = secs(t_begin, clk::now());
+  // Column panels of L go to the host in groups, through two pinned staging
+  // buffers: the copy of the next group overlaps the compression of this
+  // one.  Every off-diagonal tile of a group is compressed in one parallel
+  // loop (tiles are independent).
   const int r = static_cast<int>((n + m - 1) / m);
   std::vector<int> tm(r);
   for (int i = 0; i < r; ++i) tm[i] = static_cast<int>(std::min<int64_t>(m, n - static_cast<int64_t>(i) * m));
-  std::vector<int64_t> doff(r + 1, 0);
+  std::vector<int64_t> doff(r + 1, 0), poff(r + 1, 0);
   for (int i = 0; i < r; ++i) doff[i + 1] = doff[i] + static_cast<int64_t>(tm[i]) * tm[i];
+  for (int j = 0; j < r; ++j) poff[j + 1] = poff[j] + (n - static_cast<int64_t>(j) * m) * tm[j];
+  const int64_t stage_doubles = std::max<int64_t>(poff[1], int64_t{32} << 20);  // >= 256 MB or the first panel
+  double *stage[2] = {ctx->pinned(0, stage_doubles * 8), ctx->pinned(1, stage_doubles * 8)};
+  if (!stage[0] || !stage[1]) return fail(TLRQMC_ENOMEM, "pinned host staging allocation failed");
+  std::vector<std::pair<int, int>> groups;  // [j0, j1)
+  for (int j0 = 0; j0 < r;) {
+    int j1 = j0 + 1;
+    while (j1 < r && poff[j1 + 1] - poff[j0] <= stage_doubles) ++j1;
+    groups.push_back({j0, j1});
+    j0 = j1;
+  }
   std::vector<double> hdiag(doff[r]);
   std::vector<int32_t> ranks(static_cast<size_t>(r) * r, 0);
   std::vector<std::vector<double>> Us(static_cast<size_t>(r) * r), Vs(static_cast<size_t>(r) * r);
   int cap_hits = 0;
-  std::vector<double> panel;
-  for (int j = 0; j < r; ++j) {
-    const int64_t c0 = static_cast<int64_t>(j) * m;
-    const int64_t rows = n - c0;
-    panel.resize(static_cast<size_t>(rows) * tm[j]);
-    if (hipMemcpy2D(panel.data(), rows * sizeof(double), A + c0 * lda + c0, lda * sizeof(double),
-                    rows * sizeof(double), tm[j], hipMemcpyDeviceToHost) != hipSuccess)
-      return fail(TLRQMC_EDEVICE, "copy of the factor failed");
-    for (int t = 0; t < tm[j]; ++t)
-      for (int u = 0; u < tm[j]; ++u)
-        hdiag[doff[j] + static_cast<int64_t>(t) * tm[j] + u] = u <= t ? panel[static_cast<size_t>(u) * rows + t] : 0.0;
+  Events evs;
+  auto download = [&](size_t g) {
+    const int j0 = groups[g].first, j1 = groups[g].second;
+    double *dst = stage[g % 2];
+    for (int j = j0; j < j1; ++j) {
+      const int64_t c0 = static_cast<int64_t>(j) * m, rows = n - c0;
+      if (hipMemcpy2DAsync(dst + (poff[j] - poff[j0]), rows * sizeof(double), A + c0 * lda + c0, lda * sizeof(double),
+                           rows * sizeof(double), tm[j], hipMemcpyDeviceToHost, s) != hipSuccess)
+        return false;
+    }
+    hipEvent_t e = evs.make();
+    return e && hipEventRecord(e, s) == hipSuccess;
+  };
+  if (!download(0)) return fail(TLRQMC_EDEVICE, "copy of the factor failed");
+  for (size_t g = 0; g < groups.size(); ++g) {
+    const auto t_dl = clk::now();
+    if (hipEventSynchronize(evs.evs[g]) != hipSuccess) return fail(TLRQMC_EDEVICE, "copy of the factor failed");
+    if (g + 1 < groups.size() && !download(g + 1)) return fail(TLRQMC_EDEVICE, "copy of the factor failed");
+    const auto t_cp = clk::now();
+    phase[1] += secs(t_dl, t_cp);
+    const int j0 = groups[g].first, j1 = groups[g].second;
+    const double *src = stage[g % 2];
+    std::vector<std::pair<int, int>> tiles;
+    for (int j = j0; j < j1; ++j) {
+      const int64_t rows = n - static_cast<int64_t>(j) * m;
+      const double *panel = src + (poff[j] - poff[j0]);
+      for (int t = 0; t < tm[j]; ++t)
+        for (int u = 0; u < tm[j]; ++u)
+          hdiag[doff[j] + static_cast<int64_t>(t) * tm[j] + u] = u <= t ? panel[static_cast<size_t>(u) * rows + t] : 0.0;
+      for (int i = j + 1; i < r; ++i) tiles.push_back({i, j});
+    }
     int hits = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : hits)
-    for (int i = j + 1; i < r; ++i) {
+    for (size_t q = 0; q < tiles.size(); ++q) {
+      const int i = tiles[q].first, j = tiles[q].second;
+      const int64_t c0 = static_cast<int64_t>(j) * m, rows = n - c0;
+      const double *T = src + (poff[j] - poff[j0]) + (static_cast<int64_t>(i) * m - c0);
       bool capped = false;
-      const double *T = panel.data() + (static_cast<int64_t>(i) * m - c0);
       const int k = compress_tile(T, rows, tm[i], tm[j], tol, max_rank, Us[static_cast<size_t>(i) * r + j],
                                   Vs[static_cast<size_t>(i) * r + j], capped);
       ranks[static_cast<size_t>(i) * r + j] = k;
       hits += capped ? 1 : 0;
     }
     cap_hits += hits;
+    phase[2] += secs(t_cp, clk::now());
   }
   Aguard.reset();
+  const auto t_layout = clk::now();
   std::vector<double> hU, hV;
   for (int i = 1; i < r; ++i)
     for (int j = 0; j < i; ++j) {
@@ -501,6 +519,8 @@ int tlr_factor(tlrqmc_ctx *ctx, int64_t n, const tlrqmc_cov *cov, const int32_t 
     }
   st = factor_build(ctx, n, m, p.data(), hdiag.data(), ranks.data(), hU.data(), hV.data(), cap_hits, out);
   if (st) return st;
+  phase[3] = secs(t_layout, clk::now());
+  for (int k = 0; k < 4; ++k) (*out)->setup_seconds[k] = phase[k];
   return cap_hits > 0 ? TLRQMC_WARN_RANKCAP : TLRQMC_OK;
 }
 

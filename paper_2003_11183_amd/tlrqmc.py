@@ -44,7 +44,7 @@ class Cov(C.Structure):
 class FactorInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("m", C.c_int32), ("r", C.c_int32), ("k_tot", C.c_int64),
                 ("k_max", C.c_int32), ("cap_hits", C.c_int32), ("diag_doubles", C.c_int64),
-                ("uv_doubles", C.c_int64), ("device_bytes", C.c_int64)]
+                ("uv_doubles", C.c_int64), ("device_bytes", C.c_int64), ("setup_seconds", C.c_double * 4)]
 
 
 class QmcOpts(C.Structure):
@@ -58,6 +58,26 @@ class Result(C.Structure):
                 ("rel_err", C.c_double), ("log_p_shift", C.c_double * 64), ("n_dead", C.c_int64),
                 ("seconds", C.c_double), ("kernel_seconds", C.c_double * 5),
                 ("kernel_busy_seconds", C.c_double * 5), ("kernel_launches", C.c_int64 * 5), ("n_shifts", C.c_int32), ("chunks", C.c_int32)]
+
+
+class Request(C.Structure):
+    _fields_ = [("n", C.c_int64), ("cov", Cov), ("a", C.c_void_p), ("b", C.c_void_p), ("nu", C.c_double),
+                ("m", C.c_int32), ("max_rank", C.c_int32), ("tol", C.c_double), ("reorder", C.c_int32),
+                ("reserved", C.c_int32), ("qmc", QmcOpts)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("t_submit", C.c_double), ("t_admit", C.c_double), ("t_ready", C.c_double),
+                ("t_start", C.c_double), ("t_done", C.c_double), ("reserved_bytes", C.c_int64),
+                ("factor_bytes", C.c_int64), ("chunk_samples", C.c_int64), ("slots", C.c_int32),
+                ("concurrency", C.c_int32), ("status", C.c_int32), ("reserved", C.c_int32)]
+
+
+class ServerInfo(C.Structure):
+    _fields_ = [("budget_bytes", C.c_int64), ("reserved_bytes", C.c_int64), ("peak_reserved_bytes", C.c_int64),
+                ("arena_in_use_bytes", C.c_int64), ("arena_peak_bytes", C.c_int64), ("steps", C.c_int64),
+                ("launches", C.c_int64), ("slot_steps", C.c_int64), ("max_active_slots", C.c_int64),
+                ("queued", C.c_int32), ("in_setup", C.c_int32), ("ready", C.c_int32), ("running", C.c_int32)]
 
 
 _lib = None
@@ -82,6 +102,11 @@ SIGNATURES = {
                            C.POINTER(Result)]),
     "tlrqmc_sample_logp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                                      C.POINTER(QmcOpts), C.c_int32, C.c_int64, C.c_int64, C.c_void_p]),
+    "tlrqmc_server_create": (C.c_int, [C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)]),
+    "tlrqmc_server_submit": (C.c_int, [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_uint64)]),
+    "tlrqmc_server_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int32, C.POINTER(Result), C.POINTER(RequestInfo)]),
+    "tlrqmc_server_stats": (C.c_int, [C.c_void_p, C.POINTER(ServerInfo)]),
+    "tlrqmc_server_destroy": (C.c_int, [C.c_void_p]),
 }
 
 
@@ -238,7 +263,9 @@ class Factor:
     def stats(self) -> dict:
         inf = FactorInfo()
         _check(lib().tlrqmc_factor_stats(self.handle, C.byref(inf)))
-        return {k: getattr(inf, k) for k, _ in FactorInfo._fields_}
+        out = {k: getattr(inf, k) for k, _ in FactorInfo._fields_}
+        out["setup_seconds"] = dict(zip(("cholesky", "download", "compress", "layout"), inf.setup_seconds))
+        return out
 
     def export(self):
         """(perm, diag list, ranks, U dict, V dict) in the exchange layout."""
@@ -341,6 +368,69 @@ def sample_logp(ctx: Context, factor: Factor, a, b, nu: float, N: int, M: int, s
     _check(lib().tlrqmc_sample_logp(ctx.handle, factor.handle, a.ctypes.data, b.ctypes.data, float(nu),
                                     C.byref(o), int(shift), int(k0), int(count), out.ctypes.data))
     return out
+
+
+class Server:
+    """Request server (continuous batching with footprint admission) on ctx's device.
+
+    submit() copies the request and returns a ticket; result(ticket) waits
+    for it and returns the result dict with an 'info' entry (timings in
+    seconds since the server started, reservation, slots)."""
+
+    def __init__(self, ctx: Context, budget_bytes: int):
+        self.ctx = ctx
+        h = C.c_void_p()
+        _check(lib().tlrqmc_server_create(ctx.handle, int(budget_bytes), C.byref(h)))
+        self.handle = h
+
+    def submit(self, cov: dict, a, b, N: int, M: int, seed: int, nu: float = 0.0, m: int = 128,
+               tol: float = 1e-5, max_rank: int = 0, reorder: bool = False, precision: int = 0) -> int:
+        a, b = _f64(a), _f64(b)
+        n = len(a)
+        if b.shape != (n,):
+            raise ValueError("a and b must have the same length")
+        cv, keep = _cov(cov, n)
+        req = Request(n, cv, a.ctypes.data, b.ctypes.data, float(nu), int(m), int(max_rank), float(tol),
+                      int(bool(reorder)), 0, _opts(N, M, seed, precision, None, False, 0))
+        t = C.c_uint64()
+        _check(lib().tlrqmc_server_submit(self.handle, C.byref(req), C.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int, wait_s: float = 0.0):
+        """Result dict, or None while the request is pending (after waiting
+        up to wait_s seconds; wait_s < 0 waits until it is done)."""
+        res, inf = Result(), RequestInfo()
+        wait_ms = -1 if wait_s < 0 else int(min(wait_s * 1e3, 2 ** 31 - 1))
+        st = lib().tlrqmc_server_poll(self.handle, int(ticket), wait_ms, C.byref(res), C.byref(inf))
+        if st == PENDING:
+            return None
+        _check(st)
+        out = _result(res, st)
+        out["info"] = {k: getattr(inf, k) for k, _ in RequestInfo._fields_}
+        return out
+
+    def result(self, ticket: int, timeout_s: float = -1.0):
+        """Wait for a ticket's result (TimeoutError after timeout_s > 0 seconds)."""
+        out = self.poll(ticket, timeout_s)
+        if out is None:
+            raise TimeoutError(f"request {ticket} not done after {timeout_s} s")
+        return out
+
+    def stats(self) -> dict:
+        inf = ServerInfo()
+        _check(lib().tlrqmc_server_stats(self.handle, C.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in ServerInfo._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(lib().tlrqmc_server_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def log_relative_gap(x: float, y: float) -> float:
