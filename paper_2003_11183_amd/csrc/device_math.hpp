@@ -315,36 +315,74 @@ __device__ __forceinline__ float horner32(const float (&c)[N], float s) {
   return acc;
 }
 
-// Precision form of the one-sided step: Phi(bh), log Phi(bh) and the
-// quantile in FP32 in the centre (|bh| <= 11, w' = -log(4u(1-u)) < 6.25),
-// with the FP64 path for the tails.  The running sum of log P stays FP64;
-// the FP32 parts carry about 1e-7 relative error, far below the QMC error.
-__device__ inline double sov_step_upper_mixed(double bh, double w, double &y) {
-  const double ab = fabs(bh);
-  if (!(ab <= 11.0)) return sov_step_upper(bh, w, y);
-  const float z = static_cast<float>(ab * M_SQRT1_2);
-  const float t = (z - kErfcx32K) * __builtin_amdgcn_rcpf(z + kErfcx32K);
-  const float g = horner32(kErfcx32, (t - kErfcx32C) * kErfcx32H);
-  const float ex = g * (1.0f - t) * 0.25f;  // erfcx(z) / 2
-  const double p = bh * bh;
-  const double a = 0.5 * p;
-  const double al = 0.5 * fma(bh, bh, -p);
-  const float q = ex * __builtin_amdgcn_exp2f(static_cast<float>(-(a + al) * M_LOG2E));
-  const bool neg = bh < 0.0;
-  const float e = neg ? q : 1.0f - q;
-  // log of ex (below zero) or of 1 - q (above): one hardware log2
-  const float lg = __builtin_amdgcn_logf(neg ? ex : e) * static_cast<float>(M_LN2);
-  const double le = neg ? static_cast<double>(lg) - a - al : static_cast<double>(lg);
-  const double u = w * static_cast<double>(e);
-  const double q4 = 4.0 * u * (1.0 - u);
-  const float wv = -__builtin_amdgcn_logf(static_cast<float>(q4)) * static_cast<float>(M_LN2);
-  if (wv < 6.25f) {
-    const float pw = horner32(kInv32, (wv - kInv32C) * kInv32H);
-    y = M_SQRT2 * (2.0 * u - 1.0) * static_cast<double>(pw);
-  } else {
-    y = Phi_inv(special_table(), u);
+// erfcx(z) / 2 in FP32 for z >= 0: the rational-map polynomial up to
+// z = 8, the asymptotic series 1/(z sqrt(pi)) (1 - v + 3v^2 - 15v^3 +
+// 105v^4 - 945v^5), v = 1/(2z^2), beyond (error below 3e-9 there).
+__device__ __forceinline__ float half_erfcx32(float z) {
+  if (z <= kErfcx32Zmax) {
+    const float t = (z - kErfcx32K) * __builtin_amdgcn_rcpf(z + kErfcx32K);
+    const float g = horner32(kErfcx32, (t - kErfcx32C) * kErfcx32H);
+    return g * (1.0f - t) * 0.25f;
   }
-  return le;
+  const float r = __builtin_amdgcn_rcpf(z);
+  const float v = 0.5f * r * r;
+  const float sr = fmaf(fmaf(fmaf(fmaf(fmaf(-945.0f, v, 105.0f), v, -15.0f), v, 3.0f), v, -1.0f), v, 1.0f);
+  return (0.5f * 0.56418958354775628f) * r * sr;
+}
+
+// Precision form of the one-sided step: Phi(bh), log Phi(bh) and the
+// quantile with FP32 special functions, FP64 where precision is made.
+//   q = Phi(-|bh|) = erfcx(|bh|/sqrt2) exp(-bh^2/2) / 2: erfcx in FP32, the
+//     exponent bh^2/2 split exactly in FP64 and reduced to 2^-(k + f) there.
+//   log Phi(bh) = log(erfcx/2) - bh^2/2 below zero (FP32 log, FP64 sum), and
+//     log1p(-q) = -2 atanh(q / (2 - q)) above (FP32 series).
+//   u = w Phi(bh) and its complement c = 1 - u are formed in FP64 without
+//     cancellation (c = (1 - w) + w q above zero), and
+//     Phi^-1(u) = sqrt2 (u - c) p(w'), w' = -log(4 p (1 - p)), p = min(u, c),
+//     with p(w') in FP32 out to w' = 90 (p down to 1e-36).
+// Rows outside (bh < -13.1 where q leaves the FP32 range, infinite limits,
+// p < 1e-36) take the FP64 step.  The FP32 parts carry about 2e-7 relative
+// error; the running sum of log P stays FP64.
+__device__ inline double sov_step_upper_fp32(double bh, double w, double &y) {
+  constexpr float kLn2f = 0.69314718055994531f;
+  if (bh >= -13.1 && bh < INFINITY) {
+    const double ab = fabs(bh);
+    const float ex = half_erfcx32(static_cast<float>(ab * M_SQRT1_2));
+    const double p2 = bh * bh;
+    const double a = 0.5 * p2;
+    const double al = 0.5 * fma(bh, bh, -p2);  // bh^2 / 2 = a + al exactly
+    const double tt = (a + al) * M_LOG2E;
+    const double kf = floor(tt);
+    const float q = __builtin_amdgcn_ldexpf(ex * __builtin_amdgcn_exp2f(-static_cast<float>(tt - kf)),
+                                             -static_cast<int>(kf));
+    const double qd = static_cast<double>(q);
+    const bool neg = bh < 0.0;
+    // log Phi(bh): both forms are cheap, the sign selects
+    const double l_neg = static_cast<double>(__builtin_amdgcn_logf(ex) * kLn2f) - a - al;
+    const float v = q * __builtin_amdgcn_rcpf(2.0f - q);
+    const float v2 = v * v;
+    const float at = fmaf(fmaf(fmaf(fmaf(fmaf(fmaf(fmaf(1.0f / 15.0f, v2, 1.0f / 13.0f), v2, 1.0f / 11.0f), v2,
+                                              1.0f / 9.0f), v2, 1.0f / 7.0f), v2, 0.2f), v2, 1.0f / 3.0f), v2, 1.0f);
+    const double le = neg ? l_neg : static_cast<double>(-2.0f * v * at);
+    const double u = neg ? w * qd : fma(-w, qd, w);
+    const double c = neg ? 1.0 - u : fma(w, qd, 1.0 - w);
+    const double pm = fmin(u, c);
+    if (pm >= 1e-36) {
+      const float pf = static_cast<float>(pm);
+      const float wv = -__builtin_amdgcn_logf(4.0f * pf * (1.0f - pf)) * kLn2f;
+      float pw;
+      if (wv < 6.25f) {
+        pw = horner32(kInv32, (wv - kInv32C) * kInv32H);
+      } else {
+        const float sq = __builtin_amdgcn_sqrtf(wv);
+        pw = sq < kInv32Split ? horner32(kInv32T0, (sq - kInv32T0C) * kInv32T0H)
+                              : horner32(kInv32T1, (sq - kInv32T1C) * kInv32T1H);
+      }
+      y = M_SQRT2 * (u - c) * static_cast<double>(pw);
+      return le;
+    }
+  }
+  return sov_step_upper(bh, w, y);
 }
 
 // Regularized incomplete gamma: returns P(a, x) and sets q = Q(a, x).

@@ -148,6 +148,9 @@ T_MAX32 = (Z_MAX32 - K32) / (Z_MAX32 + K32)
 DEG32_ERFCX = 11
 DEG32_INV = 10
 W_MAX32 = 6.25
+# float32 tail of erfinv in sqrt(w), out to w = 90 (u down to about 3e-40,
+# below the float32 normal range): two intervals split at sqrt(w) = 4.5
+INV32_TAIL = [(2.5, 4.5, 8), (4.5, 9.5, 8)]
 
 
 def erfcx_scaled_t32(t):
@@ -225,11 +228,19 @@ def main():
     # float32 polynomials (compile-time constants: 32-bit literals in the code)
     c32e, m32e, h32e = fit32(erfcx_scaled_t32, -1, T_MAX32, DEG32_ERFCX, "erfcx g(t), z in [0, 8]")
     c32i, m32i, h32i = fit32(erfinv_p_of_w, 0.0, W_MAX32, DEG32_INV, "erfinv p(w), w in [0, 6.25]")
+    tails32 = [fit32(erfinv_p_of_sqrtw, lo, hi, deg, f"erfinv p(sqrt w), sqrt w in [{lo}, {hi}]")
+               for lo, hi, deg in INV32_TAIL]
     out.append(f"constexpr float kErfcx32K = {K32!r}f, kErfcx32Zmax = {Z_MAX32!r}f;")
     out.append(f"constexpr float kErfcx32C = {float(np.float32(m32e))!r}f, kErfcx32H = {float(np.float32(1.0 / h32e))!r}f;")
     out.append(f"constexpr float kErfcx32[{len(c32e)}] = {{" + ", ".join(f"{x!r}f" for x in c32e) + "};")
     out.append(f"constexpr float kInv32C = {float(np.float32(m32i))!r}f, kInv32H = {float(np.float32(1.0 / h32i))!r}f;")
     out.append(f"constexpr float kInv32[{len(c32i)}] = {{" + ", ".join(f"{x!r}f" for x in c32i) + "};")
+    for k, (cf, mc, hh) in enumerate(tails32):
+        lo, hi, _ = INV32_TAIL[k]
+        out.append(f"// float32 erfinv tail {k}: sqrt(w) in [{lo}, {hi}]")
+        out.append(f"constexpr float kInv32T{k}C = {float(np.float32(mc))!r}f, kInv32T{k}H = {float(np.float32(1.0 / hh))!r}f;")
+        out.append(f"constexpr float kInv32T{k}[{len(cf)}] = {{" + ", ".join(f"{x!r}f" for x in cf) + "};")
+    out.append(f"constexpr float kInv32Split = {INV32_TAIL[0][1]!r}f;")
     body = ",\n    ".join(f"{x:.17e}" for x in table)
     out.append(f"constexpr int kSpecialTableSize = {len(table)};")
     out.append(f"TLRQMC_SPECIAL_TABLE double kSpecialTable[{len(table)}] = {{\n    {body}}};")

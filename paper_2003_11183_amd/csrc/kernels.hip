@@ -114,7 +114,7 @@ __device__ __forceinline__ void sweep_body(const SweepParams &p, int64_t si) {
         const double at = R * al[row] - dlt;
         ldel = sov_step((at - acc[0]) * col[0], (bt - acc[0]) * col[0], w, y);
       } else {
-        ldel = MIXED ? sov_step_upper_mixed((bt - acc[0]) * col[0], w, y)
+        ldel = MIXED ? sov_step_upper_fp32((bt - acc[0]) * col[0], w, y)
                      : sov_step_upper((bt - acc[0]) * col[0], w, y);
       }
       lp += ldel;

@@ -418,6 +418,8 @@ int tlr_factor(tlrqmc_ctx *ctx, int64_t n, const tlrqmc_cov *cov, const int32_t 
   if (!ctx->blas) {
     rocblas_handle nh;
     if (rocblas_create_handle(&nh) != rocblas_status_success) return fail(TLRQMC_EDEVICE, "rocblas_create_handle failed");
+    // no atomics: the factor (and so every estimate) is reproducible bit for bit
+    rocblas_set_atomics_mode(nh, rocblas_atomics_not_allowed);
     ctx->blas = nh;
   }
   rocblas_handle h = static_cast<rocblas_handle>(ctx->blas);
