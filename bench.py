@@ -94,8 +94,8 @@ def time_form(T, ctx, F, c, precision, steps, warmup):
 # from the rocprofv3 runs summarised under profiles/.  A figure is reported
 # only while the kernel sources still have the digest it was measured on.
 TRAFFIC = {
-    ("sweep", 1): {"bytes_per_launch": 3.696e9, "digest": "4809b8c34cfea878"},
-    ("delta", 0): {"bytes_per_launch": 2.177e9, "digest": "4809b8c34cfea878"},
+    (3, "sweep", 1): {"bytes_per_launch": 3.696e9, "digest": "4809b8c34cfea878"},
+    (3, "delta", 0): {"bytes_per_launch": 2.177e9, "digest": "4809b8c34cfea878"},
 }
 KERNEL_SOURCES = ("kernels.hip", "kernels_mfma.hip", "device_math.hpp", "special_tables.hpp", "internal.hpp")
 
@@ -127,7 +127,7 @@ def roofline_of(T, results, st, c, precision, steps):
     achieved = per_launch / avg
     chip = work * samples * steps / kb[dom]
     peak = PEAK_BF16_MFMA if bound == "mfma" else PEAK_FP64_VALU
-    tr = TRAFFIC.get((dom, precision))
+    tr = TRAFFIC.get((c["id"], dom, precision))
     traffic = tr["bytes_per_launch"] if tr and tr["digest"] == kernel_digest() else None
     return {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
             "frac": achieved / peak, "traffic": traffic, "traffic_unit": "bytes/launch",
