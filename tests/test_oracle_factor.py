@@ -126,3 +126,96 @@ def test_block_reorder_constant_problem_keeps_order():
 def test_phi_density():
     assert abs(sf.phi(0.0) - 1 / math.sqrt(2 * math.pi)) < 1e-17
     assert sf.phi(np.inf) == 0.0 and sf.phi(-np.inf) == 0.0
+
+
+# ---------------------------------------------- iterative block reordering
+
+def _random_spd(n, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, n))
+    return X @ X.T / n + 0.5 * np.eye(n)
+
+
+def test_iterative_reorder_factor_is_cholesky_of_reordered_covariance():
+    g, m = 12, 16
+    xy = synth.grid_xy(g)
+    n = g * g
+    S = F.exp_cov(xy, 0.2)
+    base = F.morton_order(xy)
+    b = synth.upper_limits_uniform(n, 21)
+    a = np.full(n, -np.inf)
+    perm, L = R.iterative_block_reorder(S, a, b, m, base)
+    assert sorted(perm.tolist()) == list(range(n))
+    assert np.allclose(L, np.tril(L))
+    assert np.all(np.diag(L) > 0)
+    P = S[np.ix_(perm, perm)]
+    assert np.abs(L @ L.T - P).max() < 1e-12
+    # the blocks stay whole (the ragged last one stays last)
+    blocks = [set(base[t:t + m].tolist()) for t in range(0, n, m)]
+    for q in range(0, n, m):
+        assert set(perm[q:q + m].tolist()) in blocks
+    assert set(perm[(n // m) * m:].tolist()) == set(base[(n // m) * m:].tolist())
+
+
+def test_iterative_reorder_of_independent_blocks_is_block_reorder():
+    # With no correlation between blocks, conditioning changes neither the
+    # blocks' covariances nor their limits, so every step sees the first
+    # step's scores: the result is the plain block reordering.
+    m, r = 5, 6
+    n = m * r
+    S = np.zeros((n, n))
+    for q in range(r):
+        S[q * m:(q + 1) * m, q * m:(q + 1) * m] = _random_spd(m, 100 + q)
+    rng = np.random.default_rng(3)
+    b = rng.uniform(-0.5, 2.5, n)
+    a = b - rng.uniform(0.5, 3.0, n)
+    base = np.arange(n)
+    perm, L = R.iterative_block_reorder(S, a, b, m, base)
+    assert perm.tolist() == R.block_reorder(S, a, b, m, base).tolist()
+
+
+def test_iterative_reorder_single_block_is_univariate_conditioning():
+    n = 9
+    S = _random_spd(n, 7)
+    rng = np.random.default_rng(8)
+    b = rng.uniform(-1, 2, n)
+    a = np.full(n, -np.inf)
+    perm, L = R.iterative_block_reorder(S, a, b, n, np.arange(n))
+    order, _ = R.univariate_conditioning(S, a, b)
+    assert perm.tolist() == order.tolist()
+    assert np.abs(L - np.linalg.cholesky(S[np.ix_(order, order)])).max() < 1e-13
+
+
+def test_iterative_reorder_second_step_scores_the_conditional_problem():
+    # After the first block is chosen, the remaining blocks must be scored on
+    # the Gaussian conditional distribution given that block at its
+    # truncated mean mu = L_11 y (original coordinates): covariance
+    # S22 - S21 S11^-1 S12 and limits shifted by S21 S11^-1 mu.
+    m = 4
+    n = 3 * m
+    S = _random_spd(n, 11)
+    rng = np.random.default_rng(12)
+    b = rng.uniform(-0.5, 1.5, n)
+    a = np.full(n, -np.inf)
+    base = np.arange(n)
+    perm, L = R.iterative_block_reorder(S, a, b, m, base)
+    first = perm[:m]
+    # the first block is the plain block reordering's first choice, in its order
+    assert first.tolist() == R.block_reorder(S, a, b, m, base)[:m].tolist()
+    order, _, y = R.univariate_conditioning(S[np.ix_(first, first)], a[first], b[first], with_means=True)
+    assert order.tolist() == list(range(m))
+    S11 = S[np.ix_(first, first)]
+    mu = np.linalg.cholesky(S11) @ y
+    rest = np.array([i for i in base if i not in set(first.tolist())])
+    S21 = S[np.ix_(rest, first)]
+    C = S[np.ix_(rest, rest)] - S21 @ np.linalg.solve(S11, S21.T)
+    shift = S21 @ np.linalg.solve(S11, mu)
+    ac, bc = a[rest] - shift, b[rest] - shift
+    # score the two remaining blocks of the conditional problem
+    lps = []
+    for q in range(2):
+        sl = slice(q * m, (q + 1) * m)
+        lps.append(R.univariate_conditioning(C[sl, sl], ac[sl], bc[sl])[1])
+    winner = rest[int(np.argmin(lps)) * m:(int(np.argmin(lps)) + 1) * m]
+    assert set(perm[m:2 * m].tolist()) == set(winner.tolist())
+    assert np.abs(L @ L.T - S[np.ix_(perm, perm)]).max() < 1e-12
