@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--serve-fp64", type=int, default=12, metavar="COUNT",
                     help="of those, how many also run one at a time through the plain FP64 path")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--no-reorder-study", action="store_true",
+                    help="skip the ordering study on the n = 4,096 MVN workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (scale for HBM byte counters)")
     return ap.parse_args()
@@ -183,6 +185,7 @@ def main():
     F.free()
     torch.cuda.empty_cache()
     serve = serving(T, ctx, args.serve, args.serve_fp64, args.serve_budget_gib) if args.serve > 0 else None
+    study = None if args.no_reorder_study else reorder_study(T, ctx)
     r0 = results[-1]
     lat_ms = [1e3 * x for x in lat]
     out = {
@@ -206,6 +209,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "serving": serve,
+        "reorder_study": study,
     }
     print(json.dumps(out), flush=True)
 
@@ -263,6 +267,30 @@ def serving(T, ctx, count: int, count_fp64: int, budget_gib: float):
         res["fp64_one_at_a_time"] = {"requests": count_fp64, "latency_ms_mean": 1e3 * float(np.mean(lat64)),
                                      "throughput": work64 / el, "unit": "sample·dims/s"}
     return res
+
+
+def reorder_study(T, ctx, cid: int = 2):
+    """Orderings on one workload (n = 4,096 MVN, m = 64, rank cap 32): the
+    geometric order, block reordering, and block reordering during the
+    Cholesky factorization.  Setup seconds and the estimate's relative error
+    at the workload's N x M (the same lattice and shifts for all three)."""
+    import synth
+    c = synth.config(cid)
+    cov = {"xy": c["xy"], "beta": c["beta"]}
+    out = {"workload": c["name"], "n": c["n"], "m": c["m"], "samples": c["N"], "shifts": c["M"]}
+    for name in ("geometric", "block", "block_during_cholesky"):
+        t0 = time.perf_counter()
+        if name == "block_during_cholesky":
+            F = T.Factor.build_reordered(ctx, cov, c["a"], c["b"], c["m"], c["tol"], c["cap"])
+        else:
+            perm = T.block_reorder(cov, c["a"], c["b"], c["m"]) if name == "block" else None
+            F = T.Factor.build(ctx, cov, c["n"], c["m"], c["tol"], c["cap"], perm=perm)
+        setup = time.perf_counter() - t0
+        r = T.probability(ctx, F, c["a"], c["b"], c["N"], c["M"], c["seed_shift"], nu=c["nu"], precision=0)
+        out[name] = {"setup_s": setup, "log_p": r["log_p"], "rel_err": r["rel_err"], "k_tot": F.stats()["k_tot"],
+                     "estimate_ms": 1e3 * r["seconds"]}
+        F.free()
+    return out
 
 
 def copy_calibration(torch, mib: int):

@@ -115,6 +115,27 @@ int block_reorder(tlrqmc_ctx *ctx, int64_t n, const tlrqmc_cov *cov, const doubl
 int tlr_factor(tlrqmc_ctx *ctx, int64_t n, const tlrqmc_cov *cov, const int32_t *perm, int m,
                double tol, int max_rank, tlrqmc_factor **out);
 
+/* Block reordering during the Cholesky factorization (Section 3.3, "Block
+ * reordering during Cholesky factorization"), followed by the tile
+ * compression of tlr_factor.  The blocks are consecutive size-m chunks of
+ * the geometric order.  At each elimination step the remaining full blocks
+ * are scored with the univariate conditioning estimate of their probability
+ * on the current conditional covariance (the Schur complement) and the
+ * current conditional limits; the lowest score (lowest index on ties) is
+ * swapped into place and keeps the variable order the univariate
+ * conditioning chose; the block is factored, the panel below it solved, the
+ * later limits conditioned on the block's truncated means (a_i -= L_ij y_j,
+ * b_i -= L_ij y_j) and the Schur complement updated.  A ragged last block
+ * stays last.  Student-t problems are scored with unscaled limits.
+ *   a, b    : host, n entries, original order (as block_reorder).
+ *   perm_out: host, n entries, caller allocated, may be NULL; receives the
+ *             order (perm_out[i] = original index at position i), which is
+ *             also the factor's permutation.
+ * Errors and warnings as tlr_factor; NaN limits -> TLRQMC_EINVAL. */
+int tlr_factor_rbodr(tlrqmc_ctx *ctx, int64_t n, const tlrqmc_cov *cov, const double *a,
+                     const double *b, int m, double tol, int max_rank, int32_t *perm_out,
+                     tlrqmc_factor **out);
+
 /* Build a factor from host tiles (the exchange layout, also written by
  * tlrqmc_factor_export).  r = ceil(n / m) tiles; tile i has m_i = min(m,
  * n - i m) rows.
@@ -145,6 +166,7 @@ typedef struct {
    * the device, transfer of the factor to the host, compression of the
    * off-diagonal tiles, device layouts and upload. */
   double setup_seconds[4];
+  uint64_t checksum;    /* FNV-1a hash of the exchange arrays (bit-level identity) */
 } tlrqmc_factor_info;
 
 int tlrqmc_factor_stats(const tlrqmc_factor *f, tlrqmc_factor_info *out);
@@ -300,6 +322,7 @@ typedef struct {
   int32_t concurrency;    /* slots it may have active at once    */
   int32_t status;
   int32_t reserved;
+  uint64_t factor_checksum; /* as tlrqmc_factor_info.checksum    */
 } tlrqmc_request_info;
 
 typedef struct {

@@ -75,22 +75,6 @@ void estimate_from_parts(const std::vector<double> &part, int M, int64_t N, tlrq
 
 namespace {
 
-// Device buffers of one estimator call, released on scope exit.
-struct Scratch {
-  tlrqmc_ctx *ctx;
-  std::vector<void *> ptrs;
-  explicit Scratch(tlrqmc_ctx *c) : ctx(c) {}
-  ~Scratch() {
-    for (void *p : ptrs) ctx->dfree(p);
-  }
-  template <class T>
-  T *get(size_t count) {
-    if (count == 0) count = 1;
-    void *p = ctx->dmalloc(count * sizeof(T));
-    if (p) ptrs.push_back(p);
-    return static_cast<T *>(p);
-  }
-};
 
 // Samples per call from which the chunks run on worker streams, the number
 // of worker streams, and the device memory the chunk buffers may take.
@@ -481,6 +465,7 @@ int tlrqmc_factor_stats(const tlrqmc_factor *f, tlrqmc_factor_info *o) {
   o->uv_doubles = static_cast<int64_t>(f->h_U.size());
   o->device_bytes = f->device_bytes;
   for (int k = 0; k < 4; ++k) o->setup_seconds[k] = f->setup_seconds[k];
+  o->checksum = f->checksum;
   return TLRQMC_OK;
 }
 

@@ -287,6 +287,19 @@ int factor_build(tlrqmc_ctx *ctx, int64_t n, int m, const int32_t *perm, const d
   }
   if (hipStreamSynchronize(ctx->stream) != hipSuccess) return fail(TLRQMC_EDEVICE, "stream synchronize failed");
   f->device_bytes = total;
+  {
+    uint64_t hsh = 1469598103934665603ull;
+    auto mix = [&hsh](const void *p, size_t bytes) {
+      const unsigned char *c = static_cast<const unsigned char *>(p);
+      for (size_t i = 0; i < bytes; ++i) hsh = (hsh ^ c[i]) * 1099511628211ull;
+    };
+    mix(f->perm.data(), f->perm.size() * 4);
+    mix(f->h_diag.data(), f->h_diag.size() * 8);
+    mix(f->rank.data(), f->rank.size() * 4);
+    mix(f->h_U.data(), f->h_U.size() * 8);
+    mix(f->h_V.data(), f->h_V.size() * 8);
+    f->checksum = hsh;
+  }
   *out = guard.release();
   return TLRQMC_OK;
 }

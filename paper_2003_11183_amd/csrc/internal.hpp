@@ -27,6 +27,17 @@ constexpr int kLrRows = 64;
 
 inline int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
+// Device buffers of one call, released on scope exit (through the context's
+// allocator).
+struct Scratch {
+  tlrqmc_ctx *ctx;
+  std::vector<void *> ptrs;
+  explicit Scratch(tlrqmc_ctx *c) : ctx(c) {}
+  ~Scratch();
+  template <class T>
+  T *get(size_t count);
+};
+
 // Events created during one call, destroyed on scope exit.
 struct Events {
   std::vector<hipEvent_t> evs;
@@ -108,9 +119,22 @@ struct tlrqmc_factor {
   int64_t zp_tot = 0;
   int64_t device_bytes = 0;
   double setup_seconds[4] = {0, 0, 0, 0};  // tlr_factor phases
+  uint64_t checksum = 0;                   // FNV-1a of perm, diag, ranks, U, V
 };
 
 namespace tlrqmc {
+
+inline Scratch::~Scratch() {
+  for (void *p : ptrs) ctx->dfree(p);
+}
+
+template <class T>
+T *Scratch::get(size_t count) {
+  if (count == 0) count = 1;
+  void *p = ctx->dmalloc(count * sizeof(T));
+  if (p) ptrs.push_back(p);
+  return static_cast<T *>(p);
+}
 
 // Destroy a context's cached rocBLAS handle (setup.cpp).
 void release_blas(tlrqmc_ctx *ctx);

@@ -27,4 +27,74 @@ void launch_cov_exp(hipStream_t s, int64_t n, const double *xy_perm, double rang
   }
 }
 
+// ------------------------------------------- block reordering during Cholesky
+// The working matrix is symmetric and stored in its lower triangle
+// (column-major, leading dimension lda); columns before j0 already hold
+// factor columns.
+
+__device__ __forceinline__ double sym_at(const double *A, int64_t lda, int64_t p, int64_t q) {
+  return p >= q ? A[q * lda + p] : A[p * lda + q];
+}
+
+// Copy count diagonal blocks of size mb (mb <= m; blocks start every m
+// positions from j0) into out: block l at out + l m^2, entry (u, v) at
+// v m + u; lower triangles mirrored.
+__global__ __launch_bounds__(256) void k_pack_diag(const double *A, int64_t lda, int64_t j0, int m, int mb,
+                                                   double *out) {
+  const int l = blockIdx.y;
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= static_cast<int64_t>(m) * m) return;
+  const int u = static_cast<int>(e % m), v = static_cast<int>(e / m);
+  if (u >= mb || v >= mb) return;
+  const int64_t b0 = j0 + static_cast<int64_t>(l) * m;
+  out[static_cast<int64_t>(l) * m * m + e] = sym_at(A, lda, b0 + u, b0 + v);
+}
+
+// Row rows[k] of the matrix, every column (factor part and symmetric part),
+// into tmp + k n.
+__global__ __launch_bounds__(256) void k_gather_rows(const double *A, int64_t lda, int64_t n, int64_t j0,
+                                                     const int32_t *rows, double *tmp) {
+  const int k = blockIdx.y;
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (c >= n) return;
+  const int64_t r = rows[k];
+  tmp[static_cast<int64_t>(k) * n + c] = c < j0 ? A[c * lda + r] : sym_at(A, lda, r, c);
+}
+
+// Writes the rows rows[k] of the reordered matrix: new(P, c) = old(src[P],
+// src[c]) for the symmetric part (c >= j0) and old(src[P], c) for the factor
+// part, reading old values only from tmp (row slot[src[P]] holds old row
+// src[P]; slot maps a position in rows to its k, -1 elsewhere).
+__global__ __launch_bounds__(256) void k_scatter_rows(double *A, int64_t lda, int64_t n, int64_t j0,
+                                                      const int32_t *rows, const int32_t *src,
+                                                      const int32_t *slot, const double *tmp) {
+  const int k = blockIdx.y;
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (c >= n) return;
+  const int64_t P = rows[k];
+  const int64_t sp = src[P];
+  const double *old_row = tmp + static_cast<int64_t>(slot[sp]) * n;
+  if (c < j0) {
+    A[c * lda + P] = old_row[c];
+  } else {
+    const double v = old_row[src[c]];
+    if (P >= c) A[c * lda + P] = v;
+    else A[P * lda + c] = v;
+  }
+}
+
+void launch_pack_diag(hipStream_t s, const double *A, int64_t lda, int64_t j0, int m, int mb, int count,
+                      double *out) {
+  const int64_t mm = static_cast<int64_t>(m) * m;
+  hipLaunchKernelGGL(k_pack_diag, dim3(static_cast<unsigned>((mm + 255) / 256), static_cast<unsigned>(count)),
+                     dim3(256), 0, s, A, lda, j0, m, mb, out);
+}
+
+void launch_permute_rows(hipStream_t s, double *A, int64_t lda, int64_t n, int64_t j0, int nrows,
+                         const int32_t *rows, const int32_t *src, const int32_t *slot, double *tmp) {
+  const dim3 grid(static_cast<unsigned>((n + 255) / 256), static_cast<unsigned>(nrows));
+  hipLaunchKernelGGL(k_gather_rows, grid, dim3(256), 0, s, A, lda, n, j0, rows, tmp);
+  hipLaunchKernelGGL(k_scatter_rows, grid, dim3(256), 0, s, A, lda, n, j0, rows, src, slot, tmp);
+}
+
 }  // namespace tlrqmc

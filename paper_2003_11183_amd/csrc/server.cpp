@@ -402,6 +402,7 @@ bool tlrqmc_server::plan(Request *q) {
   q->info.chunk_samples = q->chunk;
   q->info.reserved_bytes = want;
   q->info.factor_bytes = f->device_bytes;
+  q->info.factor_checksum = f->checksum;
   return true;
 }
 

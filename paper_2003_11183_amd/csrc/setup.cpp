@@ -22,6 +22,7 @@
 #include <cstring>
 #include <functional>
 #include <memory>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -88,9 +89,11 @@ int check_cov(int64_t n, const tlrqmc_cov *c) {
 double Phi(double x) { return 0.5 * std::erfc(-x * M_SQRT1_2); }
 double phi(double x) { return std::isfinite(x) ? std::exp(-0.5 * x * x) * 0.39894228040143267794 : 0.0; }
 
-// Univariate conditioning of one block: chosen order and log of the score.
+// Univariate conditioning of one block: chosen order and log of the score;
+// y_out (optional) receives the truncated means of the whitened variables in
+// that order.
 double univariate_conditioning(int m, std::vector<double> &S, std::vector<double> &a, std::vector<double> &b,
-                               std::vector<int> &order) {
+                               std::vector<int> &order, std::vector<double> *y_out = nullptr) {
   std::vector<double> L(static_cast<size_t>(m) * m, 0.0), y(m, 0.0);
   order.resize(m);
   std::iota(order.begin(), order.end(), 0);
@@ -139,6 +142,7 @@ double univariate_conditioning(int m, std::vector<double> &S, std::vector<double
       logp = -INFINITY;
     }
   }
+  if (y_out) *y_out = y;
   return logp;
 }
 
@@ -296,80 +300,44 @@ void release_blas(tlrqmc_ctx *ctx) {
 // Kernel building the permuted covariance (kernels_setup.hip).
 void launch_cov_exp(hipStream_t s, int64_t n, const double *xy_perm, double range, double variance,
                     double nugget, double *A, int64_t lda, int64_t col0, int64_t ncols);
+// Kernels of the block reordering during the Cholesky factorization.
+void launch_pack_diag(hipStream_t s, const double *A, int64_t lda, int64_t j0, int m, int mb, int count,
+                      double *out);
+void launch_permute_rows(hipStream_t s, double *A, int64_t lda, int64_t n, int64_t j0, int nrows,
+                         const int32_t *rows, const int32_t *src, const int32_t *slot, double *tmp);
 
 }  // namespace tlrqmc
 
-using namespace tlrqmc;
+namespace tlrqmc {
+namespace {
 
-extern "C" {
+using clk = std::chrono::steady_clock;
+double secs(clk::time_point a, clk::time_point b) { return std::chrono::duration<double>(b - a).count(); }
 
-int tlrqmc_geometric_order(int64_t n, const tlrqmc_cov *cov, int32_t *perm_out) {
-  clear_error();
-  if (n < 1 || !perm_out) return fail(TLRQMC_EINVAL, "n must be >= 1 and perm_out non-null");
-  int st = check_cov(n, cov);
-  if (st) return st;
-  if (cov->kind == 1) morton(n, cov->xy, perm_out);
-  else std::iota(perm_out, perm_out + n, 0);
-  return TLRQMC_OK;
+// rocSOLVER / rocBLAS factorizations from several host threads at once (each
+// with its own handle and stream) gave factors that differed from run to run;
+// one at a time they are reproducible.  Every factorization call of the
+// library holds this lock (tile compression and layouts stay concurrent).
+std::mutex g_blas_mutex;
+
+// The context's rocBLAS handle on its stream (created on first use).
+rocblas_handle blas_of(tlrqmc_ctx *ctx) {
+  if (!ctx->blas) {
+    rocblas_handle nh;
+    if (rocblas_create_handle(&nh) != rocblas_status_success) return nullptr;
+    // no atomics: the factor (and so every estimate) is reproducible bit for bit
+    rocblas_set_atomics_mode(nh, rocblas_atomics_not_allowed);
+    ctx->blas = nh;
+  }
+  rocblas_handle h = static_cast<rocblas_handle>(ctx->blas);
+  rocblas_set_stream(h, ctx->stream);
+  return h;
 }
 
-int block_reorder(tlrqmc_ctx *, int64_t n, const tlrqmc_cov *cov, const double *a, const double *b, int m,
-                  int32_t *perm_out) {
-  clear_error();
-  if (n < 1 || m < 1 || !a || !b || !perm_out) return fail(TLRQMC_EINVAL, "bad arguments to block_reorder");
-  int st = check_cov(n, cov);
-  if (st) return st;
-  for (int64_t i = 0; i < n; ++i)
-    if (std::isnan(a[i]) || std::isnan(b[i])) return fail(TLRQMC_EINVAL, "NaN limit at variable %lld", static_cast<long long>(i));
-  std::vector<int32_t> base(n);
-  if (cov->kind == 1) morton(n, cov->xy, base.data());
-  else std::iota(base.begin(), base.end(), 0);
-  const int64_t nblk = (n + m - 1) / m;
-  const int64_t nsort = (n % m == 0) ? nblk : nblk - 1;
-  std::vector<std::vector<int32_t>> blocks(nblk);
-  std::vector<double> score(nblk);
-#pragma omp parallel for schedule(dynamic, 1)
-  for (int64_t q = 0; q < nblk; ++q) {
-    const int64_t i0 = q * m;
-    const int mb = static_cast<int>(std::min<int64_t>(m, n - i0));
-    std::vector<double> S(static_cast<size_t>(mb) * mb), al(mb), bl(mb);
-    for (int i = 0; i < mb; ++i) {
-      al[i] = a[base[i0 + i]];
-      bl[i] = b[base[i0 + i]];
-      for (int j = 0; j < mb; ++j) S[static_cast<size_t>(i) * mb + j] = cov_entry(cov, base[i0 + i], base[i0 + j]);
-    }
-    std::vector<int> order;
-    score[q] = univariate_conditioning(mb, S, al, bl, order);
-    blocks[q].resize(mb);
-    for (int i = 0; i < mb; ++i) blocks[q][i] = base[i0 + order[i]];
-  }
-  for (int64_t j = 0; j < nsort; ++j) {
-    int64_t best = j;
-    for (int64_t l = j + 1; l < nsort; ++l)
-      if (score[l] < score[best]) best = l;
-    if (best != j) {
-      std::swap(score[j], score[best]);
-      std::swap(blocks[j], blocks[best]);
-    }
-  }
-  int64_t o = 0;
-  for (auto &blk : blocks)
-    for (int32_t v : blk) perm_out[o++] = v;
-  return TLRQMC_OK;
-}
-
-int tlr_factor(tlrqmc_ctx *ctx, int64_t n, const tlrqmc_cov *cov, const int32_t *perm, int m, double tol,
-               int max_rank, tlrqmc_factor **out) {
-  clear_error();
-  if (!ctx || !out) return fail(TLRQMC_EINVAL, "null context or output");
-  *out = nullptr;
-  if (n < 1 || m < 1) return fail(TLRQMC_EINVAL, "n and m must be >= 1");
-  if (!(tol >= 0.0)) return fail(TLRQMC_EINVAL, "tol must be >= 0");
-  if (max_rank < 0) return fail(TLRQMC_EINVAL, "max_rank must be >= 0");
-  int st = check_cov(n, cov);
-  if (st) return st;
-  if (hipSetDevice(ctx->device) != hipSuccess) return fail(TLRQMC_EDEVICE, "hipSetDevice failed");
-  std::vector<int32_t> p(n);
+// Validated permutation, or the geometric order (Morton for locations,
+// identity for a dense matrix) when perm is null.
+int order_of(int64_t n, const tlrqmc_cov *cov, const int32_t *perm, std::vector<int32_t> &p) {
+  p.resize(n);
   if (perm) {
     std::vector<uint8_t> seen(n, 0);
     for (int64_t i = 0; i < n; ++i) {
@@ -382,16 +350,13 @@ int tlr_factor(tlrqmc_ctx *ctx, int64_t n, const tlrqmc_cov *cov, const int32_t 
   } else {
     std::iota(p.begin(), p.end(), 0);
   }
-  using clk = std::chrono::steady_clock;
-  auto secs = [](clk::time_point a, clk::time_point b) { return std::chrono::duration<double>(b - a).count(); };
-  double phase[4] = {0, 0, 0, 0};
-  const auto t_begin = clk::now();
+  return TLRQMC_OK;
+}
+
+// The covariance in order p on the device, column-major, leading dimension lda.
+int build_cov(tlrqmc_ctx *ctx, int64_t n, const tlrqmc_cov *cov, const std::vector<int32_t> &p, double *A,
+              int64_t lda) {
   hipStream_t s = ctx->stream;
-  const int64_t lda = round_up(n, 64);
-  double *A = static_cast<double *>(ctx->dmalloc(static_cast<size_t>(lda) * n * sizeof(double)));
-  if (!A) return fail(TLRQMC_ENOMEM, "device allocation of the %lld x %lld covariance failed",
-                      static_cast<long long>(n), static_cast<long long>(n));
-  std::unique_ptr<double, std::function<void(double *)>> Aguard(A, [ctx](double *q) { ctx->dfree(q); });
   // covariance in integration order, column-major
   if (cov->kind == 1) {
     std::vector<double> xyp(2 * n);
@@ -414,31 +379,36 @@ int tlr_factor(tlrqmc_ctx *ctx, int64_t n, const tlrqmc_cov *cov, const int32_t 
         return fail(TLRQMC_EDEVICE, "copy of the covariance failed");
     }
   }
-  // dense Cholesky on the device (lower triangle)
-  if (!ctx->blas) {
-    rocblas_handle nh;
-    if (rocblas_create_handle(&nh) != rocblas_status_success) return fail(TLRQMC_EDEVICE, "rocblas_create_handle failed");
-    // no atomics: the factor (and so every estimate) is reproducible bit for bit
-    rocblas_set_atomics_mode(nh, rocblas_atomics_not_allowed);
-    ctx->blas = nh;
-  }
-  rocblas_handle h = static_cast<rocblas_handle>(ctx->blas);
-  rocblas_set_stream(h, s);
+  return TLRQMC_OK;
+}
+
+// Dense Cholesky (lower) of the n x n matrix A on the device.
+int device_potrf(tlrqmc_ctx *ctx, rocblas_handle h, int64_t n, double *A, int64_t lda, int64_t col0, int m) {
+  rocblas_int *dinfo = static_cast<rocblas_int *>(ctx->dmalloc(sizeof(rocblas_int)));
+  if (!dinfo) return fail(TLRQMC_ENOMEM, "device allocation failed");
+  std::unique_ptr<rocblas_int, std::function<void(rocblas_int *)>> iguard(dinfo, [ctx](rocblas_int *q) { ctx->dfree(q); });
+  rocblas_int info = 0;
   {
-    rocblas_int *dinfo = static_cast<rocblas_int *>(ctx->dmalloc(sizeof(rocblas_int)));
-    if (!dinfo) return fail(TLRQMC_ENOMEM, "device allocation failed");
-    std::unique_ptr<rocblas_int, std::function<void(rocblas_int *)>> iguard(dinfo, [ctx](rocblas_int *q) { ctx->dfree(q); });
-    rocblas_int info = 0;
+    std::lock_guard<std::mutex> g(g_blas_mutex);
     if (rocsolver_dpotrf(h, rocblas_fill_lower, static_cast<rocblas_int>(n), A, static_cast<rocblas_int>(lda), dinfo) !=
             rocblas_status_success ||
-        hipMemcpyAsync(&info, dinfo, sizeof info, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
+        hipMemcpyAsync(&info, dinfo, sizeof info, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
       return fail(TLRQMC_EDEVICE, "Cholesky failed on the device");
-    if (info > 0)
-      return fail(TLRQMC_ENOTSPD, "covariance not positive definite at column %lld (tile %lld)",
-                  static_cast<long long>(info - 1), static_cast<long long>((info - 1) / m));
   }
-  phase[0] = secs(t_begin, clk::now());
+  if (info > 0)
+    return fail(TLRQMC_ENOTSPD, "covariance not positive definite at column %lld (tile %lld)",
+                static_cast<long long>(col0 + info - 1), static_cast<long long>((col0 + info - 1) / m));
+  return TLRQMC_OK;
+}
+
+// From the dense factor L (lower part of A, order p) to the TLR factor:
+// download by panels, compress the off-diagonal tiles, build the layouts.
+int compress_build(tlrqmc_ctx *ctx, double *A, int64_t lda, int64_t n, int m, const std::vector<int32_t> &p,
+                   double tol, int max_rank, double *phase, std::unique_ptr<double, std::function<void(double *)>> &Aguard,
+                   tlrqmc_factor **out) {
+  hipStream_t s = ctx->stream;
+  int st;
   // Column panels of L go to the host in groups, through two pinned staging
   // buffers: the copy of the next group overlaps the compression of this
   // one.  Every off-diagonal tile of a group is compressed in one parallel
@@ -524,6 +494,249 @@ int tlr_factor(tlrqmc_ctx *ctx, int64_t n, const tlrqmc_cov *cov, const int32_t 
   phase[3] = secs(t_layout, clk::now());
   for (int k = 0; k < 4; ++k) (*out)->setup_seconds[k] = phase[k];
   return cap_hits > 0 ? TLRQMC_WARN_RANKCAP : TLRQMC_OK;
+}
+
+}  // namespace
+}  // namespace tlrqmc
+
+using namespace tlrqmc;
+
+extern "C" {
+
+int tlrqmc_geometric_order(int64_t n, const tlrqmc_cov *cov, int32_t *perm_out) {
+  clear_error();
+  if (n < 1 || !perm_out) return fail(TLRQMC_EINVAL, "n must be >= 1 and perm_out non-null");
+  int st = check_cov(n, cov);
+  if (st) return st;
+  if (cov->kind == 1) morton(n, cov->xy, perm_out);
+  else std::iota(perm_out, perm_out + n, 0);
+  return TLRQMC_OK;
+}
+
+int block_reorder(tlrqmc_ctx *, int64_t n, const tlrqmc_cov *cov, const double *a, const double *b, int m,
+                  int32_t *perm_out) {
+  clear_error();
+  if (n < 1 || m < 1 || !a || !b || !perm_out) return fail(TLRQMC_EINVAL, "bad arguments to block_reorder");
+  int st = check_cov(n, cov);
+  if (st) return st;
+  for (int64_t i = 0; i < n; ++i)
+    if (std::isnan(a[i]) || std::isnan(b[i])) return fail(TLRQMC_EINVAL, "NaN limit at variable %lld", static_cast<long long>(i));
+  std::vector<int32_t> base(n);
+  if (cov->kind == 1) morton(n, cov->xy, base.data());
+  else std::iota(base.begin(), base.end(), 0);
+  const int64_t nblk = (n + m - 1) / m;
+  const int64_t nsort = (n % m == 0) ? nblk : nblk - 1;
+  std::vector<std::vector<int32_t>> blocks(nblk);
+  std::vector<double> score(nblk);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t q = 0; q < nblk; ++q) {
+    const int64_t i0 = q * m;
+    const int mb = static_cast<int>(std::min<int64_t>(m, n - i0));
+    std::vector<double> S(static_cast<size_t>(mb) * mb), al(mb), bl(mb);
+    for (int i = 0; i < mb; ++i) {
+      al[i] = a[base[i0 + i]];
+      bl[i] = b[base[i0 + i]];
+      for (int j = 0; j < mb; ++j) S[static_cast<size_t>(i) * mb + j] = cov_entry(cov, base[i0 + i], base[i0 + j]);
+    }
+    std::vector<int> order;
+    score[q] = univariate_conditioning(mb, S, al, bl, order);
+    blocks[q].resize(mb);
+    for (int i = 0; i < mb; ++i) blocks[q][i] = base[i0 + order[i]];
+  }
+  for (int64_t j = 0; j < nsort; ++j) {
+    int64_t best = j;
+    for (int64_t l = j + 1; l < nsort; ++l)
+      if (score[l] < score[best]) best = l;
+    if (best != j) {
+      std::swap(score[j], score[best]);
+      std::swap(blocks[j], blocks[best]);
+    }
+  }
+  int64_t o = 0;
+  for (auto &blk : blocks)
+    for (int32_t v : blk) perm_out[o++] = v;
+  return TLRQMC_OK;
+}
+
+int tlr_factor(tlrqmc_ctx *ctx, int64_t n, const tlrqmc_cov *cov, const int32_t *perm, int m, double tol,
+               int max_rank, tlrqmc_factor **out) {
+  clear_error();
+  if (!ctx || !out) return fail(TLRQMC_EINVAL, "null context or output");
+  *out = nullptr;
+  if (n < 1 || m < 1) return fail(TLRQMC_EINVAL, "n and m must be >= 1");
+  if (!(tol >= 0.0)) return fail(TLRQMC_EINVAL, "tol must be >= 0");
+  if (max_rank < 0) return fail(TLRQMC_EINVAL, "max_rank must be >= 0");
+  int st = check_cov(n, cov);
+  if (st) return st;
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(TLRQMC_EDEVICE, "hipSetDevice failed");
+  std::vector<int32_t> p;
+  if ((st = order_of(n, cov, perm, p))) return st;
+  double phase[4] = {0, 0, 0, 0};
+  const auto t_begin = clk::now();
+  const int64_t lda = round_up(n, 64);
+  double *A = static_cast<double *>(ctx->dmalloc(static_cast<size_t>(lda) * n * sizeof(double)));
+  if (!A) return fail(TLRQMC_ENOMEM, "device allocation of the %lld x %lld covariance failed",
+                      static_cast<long long>(n), static_cast<long long>(n));
+  std::unique_ptr<double, std::function<void(double *)>> Aguard(A, [ctx](double *q) { ctx->dfree(q); });
+  if ((st = build_cov(ctx, n, cov, p, A, lda))) return st;
+  rocblas_handle h = blas_of(ctx);
+  if (!h) return fail(TLRQMC_EDEVICE, "rocblas_create_handle failed");
+  if ((st = device_potrf(ctx, h, n, A, lda, 0, m))) return st;
+  phase[0] = secs(t_begin, clk::now());
+  return compress_build(ctx, A, lda, n, m, p, tol, max_rank, phase, Aguard, out);
+}
+
+int tlr_factor_rbodr(tlrqmc_ctx *ctx, int64_t n, const tlrqmc_cov *cov, const double *a, const double *b, int m,
+                     double tol, int max_rank, int32_t *perm_out, tlrqmc_factor **out) {
+  clear_error();
+  if (!ctx || !out || !a || !b) return fail(TLRQMC_EINVAL, "null argument");
+  *out = nullptr;
+  if (n < 1 || m < 1) return fail(TLRQMC_EINVAL, "n and m must be >= 1");
+  if (!(tol >= 0.0)) return fail(TLRQMC_EINVAL, "tol must be >= 0");
+  if (max_rank < 0) return fail(TLRQMC_EINVAL, "max_rank must be >= 0");
+  int st = check_cov(n, cov);
+  if (st) return st;
+  for (int64_t i = 0; i < n; ++i)
+    if (std::isnan(a[i]) || std::isnan(b[i])) return fail(TLRQMC_EINVAL, "NaN limit at variable %lld", static_cast<long long>(i));
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(TLRQMC_EDEVICE, "hipSetDevice failed");
+  std::vector<int32_t> p;
+  if ((st = order_of(n, cov, nullptr, p))) return st;
+  double phase[4] = {0, 0, 0, 0};
+  const auto t_begin = clk::now();
+  hipStream_t s = ctx->stream;
+  const int64_t lda = round_up(n, 64);
+  double *A = static_cast<double *>(ctx->dmalloc(static_cast<size_t>(lda) * n * sizeof(double)));
+  if (!A) return fail(TLRQMC_ENOMEM, "device allocation of the %lld x %lld covariance failed",
+                      static_cast<long long>(n), static_cast<long long>(n));
+  std::unique_ptr<double, std::function<void(double *)>> Aguard(A, [ctx](double *q) { ctx->dfree(q); });
+  if ((st = build_cov(ctx, n, cov, p, A, lda))) return st;
+  rocblas_handle h = blas_of(ctx);
+  if (!h) return fail(TLRQMC_EDEVICE, "rocblas_create_handle failed");
+  const int r = static_cast<int>((n + m - 1) / m);
+  const int nsort = (n % m == 0) ? r : r - 1;  // a ragged last block stays last
+  // limits in the working order (conditioned as the elimination proceeds)
+  std::vector<double> al(n), bl(n);
+  for (int64_t i = 0; i < n; ++i) {
+    al[i] = a[p[i]];
+    bl[i] = b[p[i]];
+  }
+  // device work buffers
+  Scratch sc(ctx);
+  const int64_t mm = static_cast<int64_t>(m) * m;
+  double *d_pack = sc.get<double>(static_cast<size_t>(std::max(nsort, 1)) * mm);
+  double *d_tmp = sc.get<double>(static_cast<size_t>(2) * m * n);
+  int32_t *d_idx = sc.get<int32_t>(static_cast<size_t>(2) * m + 2 * n);
+  double *d_y = sc.get<double>(m);
+  double *d_t = sc.get<double>(n);
+  if (!d_pack || !d_tmp || !d_idx || !d_y || !d_t) return fail(TLRQMC_ENOMEM, "device allocation failed");
+  int32_t *d_rows = d_idx, *d_src = d_idx + 2 * m, *d_slot = d_src + n;
+  double *h_pack = ctx->pinned(3, static_cast<size_t>(std::max(nsort, 1)) * mm * sizeof(double));
+  if (!h_pack) return fail(TLRQMC_ENOMEM, "pinned host allocation failed");
+  std::vector<int32_t> src(n), slot(n, -1), rows;
+  std::iota(src.begin(), src.end(), 0);
+  std::vector<double> tvec(n);
+  auto sym_block = [&](const double *blk, int mb, std::vector<double> &S) {
+    S.resize(static_cast<size_t>(mb) * mb);
+    for (int u = 0; u < mb; ++u)
+      for (int v = 0; v < mb; ++v) S[static_cast<size_t>(u) * mb + v] = blk[static_cast<size_t>(v) * m + u];
+  };
+  for (int j = 0; j < r; ++j) {
+    const int64_t j0 = static_cast<int64_t>(j) * m;
+    const int mj = static_cast<int>(std::min<int64_t>(m, n - j0));
+    // score the remaining full blocks on the current conditional problem
+    const int cnt = j < nsort ? nsort - j : 1;
+    const int mb_last = j < nsort ? m : mj;
+    launch_pack_diag(s, A, lda, j0, m, mb_last, cnt, d_pack);
+    if (hipMemcpyAsync(h_pack, d_pack, static_cast<size_t>(cnt) * mm * sizeof(double), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail(TLRQMC_EDEVICE, "copy of the diagonal blocks failed");
+    std::vector<double> score(cnt);
+    std::vector<std::vector<int>> order(cnt);
+    std::vector<std::vector<double>> ymean(cnt);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int l = 0; l < cnt; ++l) {
+      std::vector<double> S, la(al.begin() + j0 + static_cast<int64_t>(l) * m,
+                                al.begin() + j0 + static_cast<int64_t>(l) * m + mb_last),
+          lb(bl.begin() + j0 + static_cast<int64_t>(l) * m, bl.begin() + j0 + static_cast<int64_t>(l) * m + mb_last);
+      sym_block(h_pack + static_cast<int64_t>(l) * mm, mb_last, S);
+      score[l] = univariate_conditioning(mb_last, S, la, lb, order[l], &ymean[l]);
+    }
+    int t = 0;
+    for (int l = 1; l < cnt; ++l)
+      if (score[l] < score[t]) t = l;
+    // positions j0.. take the chosen block (in its univariate-conditioning
+    // order) first; the block it displaces moves to the chosen one's place
+    rows.clear();
+    for (int u = 0; u < mj; ++u) {
+      src[j0 + u] = static_cast<int32_t>(j0 + static_cast<int64_t>(t) * m + order[t][u]);
+      rows.push_back(static_cast<int32_t>(j0 + u));
+    }
+    if (t != 0)
+      for (int u = 0; u < m; ++u) {
+        const int64_t q = j0 + static_cast<int64_t>(t) * m + u;
+        src[q] = static_cast<int32_t>(j0 + u);
+        rows.push_back(static_cast<int32_t>(q));
+      }
+    bool moved = false;
+    for (int32_t q : rows) moved = moved || src[q] != q;
+    if (moved) {
+      for (size_t k = 0; k < rows.size(); ++k) slot[rows[k]] = static_cast<int32_t>(k);
+      if (hipMemcpyAsync(d_rows, rows.data(), rows.size() * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
+          hipMemcpyAsync(d_src, src.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
+          hipMemcpyAsync(d_slot, slot.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(TLRQMC_EDEVICE, "copy of the reordering failed");
+      launch_permute_rows(s, A, lda, n, j0, static_cast<int>(rows.size()), d_rows, d_src, d_slot, d_tmp);
+      if (hipStreamSynchronize(s) != hipSuccess) return fail(TLRQMC_EDEVICE, "reordering kernel failed");
+      std::vector<int32_t> np(rows.size());
+      std::vector<double> na(rows.size()), nb(rows.size());
+      for (size_t k = 0; k < rows.size(); ++k) {
+        np[k] = p[src[rows[k]]];
+        na[k] = al[src[rows[k]]];
+        nb[k] = bl[src[rows[k]]];
+      }
+      for (size_t k = 0; k < rows.size(); ++k) {
+        p[rows[k]] = np[k];
+        al[rows[k]] = na[k];
+        bl[rows[k]] = nb[k];
+      }
+      for (int32_t q : rows) {
+        src[q] = q;
+        slot[q] = -1;
+      }
+    }
+    // factor the block, solve the panel below, condition the later limits
+    // on the block's truncated means, update the Schur complement
+    double *Ajj = A + j0 * lda + j0;
+    if ((st = device_potrf(ctx, h, mj, Ajj, lda, j0, m))) return st;
+    const int64_t rest = n - j0 - mj;
+    if (rest > 0) {
+      const double one = 1.0, zero = 0.0, minus = -1.0;
+      double *P = Ajj + mj;
+      if (hipMemcpyAsync(d_y, ymean[t].data(), mj * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(TLRQMC_EDEVICE, "copy failed");
+      std::lock_guard<std::mutex> g(g_blas_mutex);
+      if (rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
+                        rocblas_diagonal_non_unit, static_cast<rocblas_int>(rest), mj, &one, Ajj,
+                        static_cast<rocblas_int>(lda), P, static_cast<rocblas_int>(lda)) != rocblas_status_success ||
+          rocblas_dgemv(h, rocblas_operation_none, static_cast<rocblas_int>(rest), mj, &one, P,
+                        static_cast<rocblas_int>(lda), d_y, 1, &zero, d_t, 1) != rocblas_status_success ||
+          rocblas_dsyrk(h, rocblas_fill_lower, rocblas_operation_none, static_cast<rocblas_int>(rest), mj, &minus, P,
+                        static_cast<rocblas_int>(lda), &one, Ajj + mj * lda + mj,
+                        static_cast<rocblas_int>(lda)) != rocblas_status_success)
+        return fail(TLRQMC_EDEVICE, "rocBLAS update failed");
+      if (hipMemcpyAsync(tvec.data(), d_t, rest * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return fail(TLRQMC_EDEVICE, "copy of the limit update failed");
+      for (int64_t i = 0; i < rest; ++i) {
+        al[j0 + mj + i] -= tvec[i];
+        bl[j0 + mj + i] -= tvec[i];
+      }
+    }
+  }
+  phase[0] = secs(t_begin, clk::now());
+  if (perm_out) std::copy(p.begin(), p.end(), perm_out);
+  return compress_build(ctx, A, lda, n, m, p, tol, max_rank, phase, Aguard, out);
 }
 
 }  // extern "C"

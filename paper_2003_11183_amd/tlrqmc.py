@@ -44,7 +44,8 @@ class Cov(C.Structure):
 class FactorInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("m", C.c_int32), ("r", C.c_int32), ("k_tot", C.c_int64),
                 ("k_max", C.c_int32), ("cap_hits", C.c_int32), ("diag_doubles", C.c_int64),
-                ("uv_doubles", C.c_int64), ("device_bytes", C.c_int64), ("setup_seconds", C.c_double * 4)]
+                ("uv_doubles", C.c_int64), ("device_bytes", C.c_int64), ("setup_seconds", C.c_double * 4),
+                ("checksum", C.c_uint64)]
 
 
 class QmcOpts(C.Structure):
@@ -70,7 +71,8 @@ class RequestInfo(C.Structure):
     _fields_ = [("t_submit", C.c_double), ("t_admit", C.c_double), ("t_ready", C.c_double),
                 ("t_start", C.c_double), ("t_done", C.c_double), ("reserved_bytes", C.c_int64),
                 ("factor_bytes", C.c_int64), ("chunk_samples", C.c_int64), ("slots", C.c_int32),
-                ("concurrency", C.c_int32), ("status", C.c_int32), ("reserved", C.c_int32)]
+                ("concurrency", C.c_int32), ("status", C.c_int32), ("reserved", C.c_int32),
+                ("factor_checksum", C.c_uint64)]
 
 
 class ServerInfo(C.Structure):
@@ -92,6 +94,8 @@ SIGNATURES = {
                                 C.c_void_p]),
     "tlr_factor": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(Cov), C.c_void_p, C.c_int, C.c_double, C.c_int,
                              C.POINTER(C.c_void_p)]),
+    "tlr_factor_rbodr": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(Cov), C.c_void_p, C.c_void_p, C.c_int,
+                                   C.c_double, C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]),
     "tlrqmc_factor_import": (C.c_int, [C.c_void_p, C.c_int64, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                        C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
     "tlrqmc_factor_stats": (C.c_int, [C.c_void_p, C.POINTER(FactorInfo)]),
@@ -259,6 +263,24 @@ class Factor:
         st = _check(lib().tlr_factor(ctx.handle, n, C.byref(cv), _ptr(p), int(m), float(tol), int(max_rank),
                                      C.byref(h)))
         return cls(ctx, h, st)
+
+    @classmethod
+    def build_reordered(cls, ctx: Context, cov: dict, a, b, m: int, tol: float,
+                        max_rank: int = 0) -> "Factor":
+        """Factor with block reordering during the Cholesky factorization
+        (tlr_factor_rbodr); its order is factor.perm."""
+        a, b = _f64(a), _f64(b)
+        n = len(a)
+        if b.shape != (n,):
+            raise ValueError("a and b must have the same length")
+        cv, keep = _cov(cov, n)
+        perm = np.empty(n, dtype=np.int32)
+        h = C.c_void_p()
+        st = _check(lib().tlr_factor_rbodr(ctx.handle, n, C.byref(cv), a.ctypes.data, b.ctypes.data, int(m),
+                                           float(tol), int(max_rank), perm.ctypes.data, C.byref(h)))
+        F = cls(ctx, h, st)
+        F.perm = perm
+        return F
 
     def stats(self) -> dict:
         inf = FactorInfo()
