@@ -27,5 +27,5 @@ module that takes them.  Every function is pinned by tests in
 ``tests/test_oracle_*.py``; none is "parity unpinned".
 """
 
-from . import lattice, special, sov, estimate, factor, reorder  # noqa: F401
+from . import lattice, special, sov, estimate, factor, reorder, skewnormal  # noqa: F401
 from .api import sample_logp, probability  # noqa: F401
