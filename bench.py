@@ -186,6 +186,7 @@ def main():
     torch.cuda.empty_cache()
     serve = serving(T, ctx, args.serve, args.serve_fp64, args.serve_budget_gib) if args.serve > 0 else None
     study = None if args.no_reorder_study else reorder_study(T, ctx)
+    client = None if args.no_reorder_study else skewnormal_client(T, ctx)
     r0 = results[-1]
     lat_ms = [1e3 * x for x in lat]
     out = {
@@ -210,6 +211,7 @@ def main():
         "cpu_baseline": cpu,
         "serving": serve,
         "reorder_study": study,
+        "skewnormal_client": client,
     }
     print(json.dumps(out), flush=True)
 
@@ -290,6 +292,36 @@ def reorder_study(T, ctx, cid: int = 2):
         out[name] = {"setup_s": setup, "log_p": r["log_p"], "rel_err": r["rel_err"], "k_tot": F.stats()["k_tot"],
                      "estimate_ms": 1e3 * r["seconds"]}
         F.free()
+    return out
+
+
+def skewnormal_client(T, ctx, g: int = 128):
+    """One skew-normal log-likelihood evaluation (Eq. 6) at n = g^2 on a grid
+    of unit distance 1/15 with sigma1 = sigma2 = 1, beta1 = beta2 = 0.3, the
+    model drawn once from SplitMix64 normals; N = 10^4 x 10 samples in the
+    precision form, tile 128; both orderings."""
+    import synth
+    n = g * g
+    xy = synth.grid_xy(g) * ((g - 1) / 15.0)
+    x = synth.workloads._normals(705, n, 0)
+    y = synth.workloads._normals(805, n, 0)
+    prm = dict(xi=0.2, sigma1=1.0, beta1=0.3, sigma2=1.0, beta2=0.3)
+    # the draw z = xi + A x + B |y| on the device through torch (input generation only)
+    import torch
+    dev = torch.device("cuda:0")
+    X = torch.tensor(xy, dtype=torch.float64, device=dev)
+    d = torch.cdist(X, X)
+    A = torch.linalg.cholesky(torch.exp(-d / prm["beta1"]))
+    B = torch.exp(-d / prm["beta2"])
+    z = (prm["xi"] + A @ torch.tensor(x, device=dev) + B @ torch.tensor(np.abs(y), device=dev)).cpu().numpy()
+    del X, d, A, B
+    torch.cuda.empty_cache()
+    out = {"n": n, "samples": 10000, "shifts": 10, "m": 128}
+    for name, order in (("geometric", 0), ("block_during_cholesky", 2)):
+        t0 = time.perf_counter()
+        r = T.skewnormal_loglik(ctx, xy, z, N=10000, M=10, seed=7, m=128, order=order, precision=1, **prm)
+        out[name] = {"seconds": time.perf_counter() - t0, "phases_s": r["seconds"], "loglik": r["loglik"],
+                     "log_prob": r["log_prob"], "rel_err": r["log_prob_rel_err"]}
     return out
 
 

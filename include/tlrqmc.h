@@ -251,6 +251,45 @@ int tlrqmc_sample_logp(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a,
                        const double *b, double nu, const tlrqmc_qmc_opts *opts, int32_t shift,
                        int64_t k0, int64_t count, double *logp_out);
 
+/* ---------------------------------------------------- skew-normal client --
+ * Log-likelihood of the skew-normal stochastic generator Z = xi 1 + A X +
+ * B |Y| (Section 5.1, Eq. 5; X, Y independent standard normal vectors) at
+ * observations z on n locations xy (host, n x 2 row-major), with A the lower
+ * Cholesky factor of sigma1^2 exp(-|h|/beta1) and B the covariance matrix
+ * sigma2^2 exp(-|h|/beta2) (Section 5.2).  Eq. 6:
+ *   loglik = n log 2 + log phi_n(z - xi 1; A A^T + B B^T)
+ *            + log Phi_n(-inf, c; Gamma),
+ *   C = A^-1 B,  Gamma = (I + C^T C)^-1,  c = Gamma C^T A^-1 (z - xi 1).
+ * The dense linear algebra runs on the device; Gamma is factored into TLR
+ * form with tile m, truncation tol and rank cap max_rank, in the geometric
+ * order of xy (order 0) or with block reordering during the Cholesky
+ * factorization (order 2), and the probability term is mvn_prob with opts.
+ *   c_out     : host, n entries, may be NULL: the upper limits c.
+ *   factor_out: may be NULL: receives the factor of Gamma (library owned,
+ *               free with tlrqmc_factor_free).
+ * Errors: TLRQMC_EINVAL for bad parameters (sigma1 > 0, beta1 > 0, sigma2
+ * >= 0, beta2 > 0, finite xi, z and xy), TLRQMC_ENOTSPD if a covariance is
+ * not positive definite, as mvn_prob otherwise. */
+typedef struct {
+  double xi, sigma1, beta1, sigma2, beta2;
+} tlrqmc_skewnormal_params;
+
+typedef struct {
+  double loglik;            /* the whole of Eq. 6, natural log              */
+  double log_density;       /* log phi_n(z - xi 1; A A^T + B B^T)           */
+  double log_prob;          /* log Phi_n(-inf, c; Gamma), estimated         */
+  double log_prob_std_err;  /* standard error of Phi_n (not of its log)     */
+  double log_prob_rel_err;  /* relative error of Phi_n                      */
+  double seconds[3];        /* linear algebra, factor of Gamma, estimator   */
+  tlrqmc_result prob;       /* the estimator's full result                  */
+} tlrqmc_skewnormal_result;
+
+int tlrqmc_skewnormal_loglik(tlrqmc_ctx *ctx, int64_t n, const double *xy, const double *z,
+                             const tlrqmc_skewnormal_params *params, int m, double tol,
+                             int max_rank, int order, const tlrqmc_qmc_opts *opts,
+                             tlrqmc_skewnormal_result *out, double *c_out,
+                             tlrqmc_factor **factor_out);
+
 /* -------------------------------------------------------------- serving --
  * A request server answers a stream of probability requests of mixed
  * dimension on the context's device (the likelihood evaluations of

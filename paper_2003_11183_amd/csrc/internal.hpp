@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -138,6 +139,22 @@ T *Scratch::get(size_t count) {
 
 // Destroy a context's cached rocBLAS handle (setup.cpp).
 void release_blas(tlrqmc_ctx *ctx);
+
+// ---- dense device linear algebra shared by the clients (setup.cpp) ----
+// The context's rocBLAS handle on its stream (rocblas_handle), and the lock
+// every rocSOLVER / rocBLAS factorization call of the library holds.
+typedef struct _rocblas_handle *rocblas_handle_t;
+rocblas_handle_t blas_handle(tlrqmc_ctx *ctx);
+std::mutex &blas_mutex();
+// Cholesky (lower) of the n x n device matrix A in place; ENOTSPD names the column.
+int device_cholesky(tlrqmc_ctx *ctx, double *A, int64_t lda, int64_t n);
+// TLR factor of the symmetric device matrix S (lower stored, leading
+// dimension lds): geometric order of xy (identity when xy is null), then
+// the Cholesky (order 0) or the block reordering during the Cholesky with
+// limits a, b (order 2), then the tile compression of tlr_factor.
+int factor_from_device_dense(tlrqmc_ctx *ctx, int64_t n, const double *S, int64_t lds, const double *a,
+                             const double *b, const double *xy, int m, double tol, int max_rank, int order,
+                             int32_t *perm_out, tlrqmc_factor **out);
 
 // ---- host lattice (lattice.cpp) ----
 std::vector<uint64_t> richtmyer_generators(int64_t dim);

@@ -83,6 +83,40 @@ __global__ __launch_bounds__(256) void k_scatter_rows(double *A, int64_t lda, in
   }
 }
 
+// A(i, j) = S(p[i], p[j]) on the lower triangle (S symmetric, lower stored).
+__global__ __launch_bounds__(256) void k_gather_sym(const double *S, int64_t lds, const int32_t *p, double *A,
+                                                    int64_t lda, int64_t n, int64_t col0) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t j = col0 + blockIdx.y;
+  if (i >= n || i < j) return;
+  A[j * lda + i] = sym_at(S, lds, p[i], p[j]);
+}
+
+// Lower triangle of the identity.
+__global__ __launch_bounds__(256) void k_set_identity(double *A, int64_t lda, int64_t n, int64_t col0) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t j = col0 + blockIdx.y;
+  if (i >= n || i < j) return;
+  A[j * lda + i] = i == j ? 1.0 : 0.0;
+}
+
+void launch_gather_sym(hipStream_t s, const double *S, int64_t lds, const int32_t *p, double *A, int64_t lda,
+                       int64_t n) {
+  for (int64_t c = 0; c < n; c += 65535) {
+    const int64_t nc = n - c < 65535 ? n - c : 65535;
+    hipLaunchKernelGGL(k_gather_sym, dim3(static_cast<unsigned>((n + 255) / 256), static_cast<unsigned>(nc)),
+                       dim3(256), 0, s, S, lds, p, A, lda, n, c);
+  }
+}
+
+void launch_set_identity(hipStream_t s, double *A, int64_t lda, int64_t n) {
+  for (int64_t c = 0; c < n; c += 65535) {
+    const int64_t nc = n - c < 65535 ? n - c : 65535;
+    hipLaunchKernelGGL(k_set_identity, dim3(static_cast<unsigned>((n + 255) / 256), static_cast<unsigned>(nc)),
+                       dim3(256), 0, s, A, lda, n, c);
+  }
+}
+
 void launch_pack_diag(hipStream_t s, const double *A, int64_t lda, int64_t j0, int m, int mb, int count,
                       double *out) {
   const int64_t mm = static_cast<int64_t>(m) * m;

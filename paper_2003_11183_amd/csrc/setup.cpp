@@ -300,6 +300,8 @@ void release_blas(tlrqmc_ctx *ctx) {
 // Kernel building the permuted covariance (kernels_setup.hip).
 void launch_cov_exp(hipStream_t s, int64_t n, const double *xy_perm, double range, double variance,
                     double nugget, double *A, int64_t lda, int64_t col0, int64_t ncols);
+void launch_gather_sym(hipStream_t s, const double *S, int64_t lds, const int32_t *p, double *A, int64_t lda,
+                       int64_t n);
 // Kernels of the block reordering during the Cholesky factorization.
 void launch_pack_diag(hipStream_t s, const double *A, int64_t lda, int64_t j0, int m, int mb, int count,
                       double *out);
@@ -496,7 +498,184 @@ int compress_build(tlrqmc_ctx *ctx, double *A, int64_t lda, int64_t n, int m, co
   return cap_hits > 0 ? TLRQMC_WARN_RANKCAP : TLRQMC_OK;
 }
 
+// Block reordering during the Cholesky factorization of A (lower part,
+// order p, limits al, bl in that order): on return A holds the factor and p,
+// al, bl the final order (al, bl conditioned).
+int rbodr_eliminate(tlrqmc_ctx *ctx, rocblas_handle h, double *A, int64_t lda, int64_t n, int m,
+                    std::vector<int32_t> &p, std::vector<double> &al, std::vector<double> &bl) {
+  hipStream_t s = ctx->stream;
+  int st;
+  const int r = static_cast<int>((n + m - 1) / m);
+  const int nsort = (n % m == 0) ? r : r - 1;  // a ragged last block stays last
+  // device work buffers
+  Scratch sc(ctx);
+  const int64_t mm = static_cast<int64_t>(m) * m;
+  double *d_pack = sc.get<double>(static_cast<size_t>(std::max(nsort, 1)) * mm);
+  double *d_tmp = sc.get<double>(static_cast<size_t>(2) * m * n);
+  int32_t *d_idx = sc.get<int32_t>(static_cast<size_t>(2) * m + 2 * n);
+  double *d_y = sc.get<double>(m);
+  double *d_t = sc.get<double>(n);
+  if (!d_pack || !d_tmp || !d_idx || !d_y || !d_t) return fail(TLRQMC_ENOMEM, "device allocation failed");
+  int32_t *d_rows = d_idx, *d_src = d_idx + 2 * m, *d_slot = d_src + n;
+  double *h_pack = ctx->pinned(3, static_cast<size_t>(std::max(nsort, 1)) * mm * sizeof(double));
+  if (!h_pack) return fail(TLRQMC_ENOMEM, "pinned host allocation failed");
+  std::vector<int32_t> src(n), slot(n, -1), rows;
+  std::iota(src.begin(), src.end(), 0);
+  std::vector<double> tvec(n);
+  auto sym_block = [&](const double *blk, int mb, std::vector<double> &S) {
+    S.resize(static_cast<size_t>(mb) * mb);
+    for (int u = 0; u < mb; ++u)
+      for (int v = 0; v < mb; ++v) S[static_cast<size_t>(u) * mb + v] = blk[static_cast<size_t>(v) * m + u];
+  };
+  for (int j = 0; j < r; ++j) {
+    const int64_t j0 = static_cast<int64_t>(j) * m;
+    const int mj = static_cast<int>(std::min<int64_t>(m, n - j0));
+    // score the remaining full blocks on the current conditional problem
+    const int cnt = j < nsort ? nsort - j : 1;
+    const int mb_last = j < nsort ? m : mj;
+    launch_pack_diag(s, A, lda, j0, m, mb_last, cnt, d_pack);
+    if (hipMemcpyAsync(h_pack, d_pack, static_cast<size_t>(cnt) * mm * sizeof(double), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail(TLRQMC_EDEVICE, "copy of the diagonal blocks failed");
+    std::vector<double> score(cnt);
+    std::vector<std::vector<int>> order(cnt);
+    std::vector<std::vector<double>> ymean(cnt);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int l = 0; l < cnt; ++l) {
+      std::vector<double> S, la(al.begin() + j0 + static_cast<int64_t>(l) * m,
+                                al.begin() + j0 + static_cast<int64_t>(l) * m + mb_last),
+          lb(bl.begin() + j0 + static_cast<int64_t>(l) * m, bl.begin() + j0 + static_cast<int64_t>(l) * m + mb_last);
+      sym_block(h_pack + static_cast<int64_t>(l) * mm, mb_last, S);
+      score[l] = univariate_conditioning(mb_last, S, la, lb, order[l], &ymean[l]);
+    }
+    int t = 0;
+    for (int l = 1; l < cnt; ++l)
+      if (score[l] < score[t]) t = l;
+    // positions j0.. take the chosen block (in its univariate-conditioning
+    // order) first; the block it displaces moves to the chosen one's place
+    rows.clear();
+    for (int u = 0; u < mj; ++u) {
+      src[j0 + u] = static_cast<int32_t>(j0 + static_cast<int64_t>(t) * m + order[t][u]);
+      rows.push_back(static_cast<int32_t>(j0 + u));
+    }
+    if (t != 0)
+      for (int u = 0; u < m; ++u) {
+        const int64_t q = j0 + static_cast<int64_t>(t) * m + u;
+        src[q] = static_cast<int32_t>(j0 + u);
+        rows.push_back(static_cast<int32_t>(q));
+      }
+    bool moved = false;
+    for (int32_t q : rows) moved = moved || src[q] != q;
+    if (moved) {
+      for (size_t k = 0; k < rows.size(); ++k) slot[rows[k]] = static_cast<int32_t>(k);
+      if (hipMemcpyAsync(d_rows, rows.data(), rows.size() * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
+          hipMemcpyAsync(d_src, src.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
+          hipMemcpyAsync(d_slot, slot.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(TLRQMC_EDEVICE, "copy of the reordering failed");
+      launch_permute_rows(s, A, lda, n, j0, static_cast<int>(rows.size()), d_rows, d_src, d_slot, d_tmp);
+      if (hipStreamSynchronize(s) != hipSuccess) return fail(TLRQMC_EDEVICE, "reordering kernel failed");
+      std::vector<int32_t> np(rows.size());
+      std::vector<double> na(rows.size()), nb(rows.size());
+      for (size_t k = 0; k < rows.size(); ++k) {
+        np[k] = p[src[rows[k]]];
+        na[k] = al[src[rows[k]]];
+        nb[k] = bl[src[rows[k]]];
+      }
+      for (size_t k = 0; k < rows.size(); ++k) {
+        p[rows[k]] = np[k];
+        al[rows[k]] = na[k];
+        bl[rows[k]] = nb[k];
+      }
+      for (int32_t q : rows) {
+        src[q] = q;
+        slot[q] = -1;
+      }
+    }
+    // factor the block, solve the panel below, condition the later limits
+    // on the block's truncated means, update the Schur complement
+    double *Ajj = A + j0 * lda + j0;
+    if ((st = device_potrf(ctx, h, mj, Ajj, lda, j0, m))) return st;
+    const int64_t rest = n - j0 - mj;
+    if (rest > 0) {
+      const double one = 1.0, zero = 0.0, minus = -1.0;
+      double *P = Ajj + mj;
+      if (hipMemcpyAsync(d_y, ymean[t].data(), mj * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(TLRQMC_EDEVICE, "copy failed");
+      std::lock_guard<std::mutex> g(g_blas_mutex);
+      if (rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
+                        rocblas_diagonal_non_unit, static_cast<rocblas_int>(rest), mj, &one, Ajj,
+                        static_cast<rocblas_int>(lda), P, static_cast<rocblas_int>(lda)) != rocblas_status_success ||
+          rocblas_dgemv(h, rocblas_operation_none, static_cast<rocblas_int>(rest), mj, &one, P,
+                        static_cast<rocblas_int>(lda), d_y, 1, &zero, d_t, 1) != rocblas_status_success ||
+          rocblas_dsyrk(h, rocblas_fill_lower, rocblas_operation_none, static_cast<rocblas_int>(rest), mj, &minus, P,
+                        static_cast<rocblas_int>(lda), &one, Ajj + mj * lda + mj,
+                        static_cast<rocblas_int>(lda)) != rocblas_status_success)
+        return fail(TLRQMC_EDEVICE, "rocBLAS update failed");
+      if (hipMemcpyAsync(tvec.data(), d_t, rest * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return fail(TLRQMC_EDEVICE, "copy of the limit update failed");
+      for (int64_t i = 0; i < rest; ++i) {
+        al[j0 + mj + i] -= tvec[i];
+        bl[j0 + mj + i] -= tvec[i];
+      }
+    }
+  }
+  return TLRQMC_OK;
+}
+
 }  // namespace
+
+std::mutex &blas_mutex() { return g_blas_mutex; }
+
+rocblas_handle_t blas_handle(tlrqmc_ctx *ctx) { return blas_of(ctx); }
+
+int device_cholesky(tlrqmc_ctx *ctx, double *A, int64_t lda, int64_t n) {
+  rocblas_handle h = blas_of(ctx);
+  if (!h) return fail(TLRQMC_EDEVICE, "rocblas_create_handle failed");
+  return device_potrf(ctx, h, n, A, lda, 0, static_cast<int>(std::max<int64_t>(n, 1)));
+}
+
+int factor_from_device_dense(tlrqmc_ctx *ctx, int64_t n, const double *S, int64_t lds, const double *a,
+                             const double *b, const double *xy, int m, double tol, int max_rank, int order,
+                             int32_t *perm_out, tlrqmc_factor **out) {
+  *out = nullptr;
+  std::vector<int32_t> p(n);
+  if (xy) morton(n, xy, p.data());
+  else std::iota(p.begin(), p.end(), 0);
+  double phase[4] = {0, 0, 0, 0};
+  const auto t_begin = clk::now();
+  hipStream_t s = ctx->stream;
+  const int64_t lda = round_up(n, 64);
+  double *A = static_cast<double *>(ctx->dmalloc(static_cast<size_t>(lda) * n * sizeof(double)));
+  if (!A) return fail(TLRQMC_ENOMEM, "device allocation of the %lld x %lld covariance failed",
+                      static_cast<long long>(n), static_cast<long long>(n));
+  std::unique_ptr<double, std::function<void(double *)>> Aguard(A, [ctx](double *q) { ctx->dfree(q); });
+  int32_t *dp = static_cast<int32_t *>(ctx->dmalloc(n * sizeof(int32_t)));
+  if (!dp) return fail(TLRQMC_ENOMEM, "device allocation failed");
+  std::unique_ptr<int32_t, std::function<void(int32_t *)>> pguard(dp, [ctx](int32_t *q) { ctx->dfree(q); });
+  if (hipMemcpyAsync(dp, p.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess)
+    return fail(TLRQMC_EDEVICE, "copy of the order failed");
+  launch_gather_sym(s, S, lds, dp, A, lda, n);
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(TLRQMC_EDEVICE, "covariance gather failed");
+  rocblas_handle h = blas_of(ctx);
+  if (!h) return fail(TLRQMC_EDEVICE, "rocblas_create_handle failed");
+  int st;
+  if (order == 2) {
+    std::vector<double> al(n), bl(n);
+    for (int64_t i = 0; i < n; ++i) {
+      al[i] = a[p[i]];
+      bl[i] = b[p[i]];
+    }
+    if ((st = rbodr_eliminate(ctx, h, A, lda, n, m, p, al, bl))) return st;
+  } else {
+    if ((st = device_potrf(ctx, h, n, A, lda, 0, m))) return st;
+  }
+  phase[0] = secs(t_begin, clk::now());
+  if (perm_out) std::copy(p.begin(), p.end(), perm_out);
+  return compress_build(ctx, A, lda, n, m, p, tol, max_rank, phase, Aguard, out);
+}
+
 }  // namespace tlrqmc
 
 using namespace tlrqmc;
@@ -612,128 +791,13 @@ int tlr_factor_rbodr(tlrqmc_ctx *ctx, int64_t n, const tlrqmc_cov *cov, const do
   if ((st = build_cov(ctx, n, cov, p, A, lda))) return st;
   rocblas_handle h = blas_of(ctx);
   if (!h) return fail(TLRQMC_EDEVICE, "rocblas_create_handle failed");
-  const int r = static_cast<int>((n + m - 1) / m);
-  const int nsort = (n % m == 0) ? r : r - 1;  // a ragged last block stays last
   // limits in the working order (conditioned as the elimination proceeds)
   std::vector<double> al(n), bl(n);
   for (int64_t i = 0; i < n; ++i) {
     al[i] = a[p[i]];
     bl[i] = b[p[i]];
   }
-  // device work buffers
-  Scratch sc(ctx);
-  const int64_t mm = static_cast<int64_t>(m) * m;
-  double *d_pack = sc.get<double>(static_cast<size_t>(std::max(nsort, 1)) * mm);
-  double *d_tmp = sc.get<double>(static_cast<size_t>(2) * m * n);
-  int32_t *d_idx = sc.get<int32_t>(static_cast<size_t>(2) * m + 2 * n);
-  double *d_y = sc.get<double>(m);
-  double *d_t = sc.get<double>(n);
-  if (!d_pack || !d_tmp || !d_idx || !d_y || !d_t) return fail(TLRQMC_ENOMEM, "device allocation failed");
-  int32_t *d_rows = d_idx, *d_src = d_idx + 2 * m, *d_slot = d_src + n;
-  double *h_pack = ctx->pinned(3, static_cast<size_t>(std::max(nsort, 1)) * mm * sizeof(double));
-  if (!h_pack) return fail(TLRQMC_ENOMEM, "pinned host allocation failed");
-  std::vector<int32_t> src(n), slot(n, -1), rows;
-  std::iota(src.begin(), src.end(), 0);
-  std::vector<double> tvec(n);
-  auto sym_block = [&](const double *blk, int mb, std::vector<double> &S) {
-    S.resize(static_cast<size_t>(mb) * mb);
-    for (int u = 0; u < mb; ++u)
-      for (int v = 0; v < mb; ++v) S[static_cast<size_t>(u) * mb + v] = blk[static_cast<size_t>(v) * m + u];
-  };
-  for (int j = 0; j < r; ++j) {
-    const int64_t j0 = static_cast<int64_t>(j) * m;
-    const int mj = static_cast<int>(std::min<int64_t>(m, n - j0));
-    // score the remaining full blocks on the current conditional problem
-    const int cnt = j < nsort ? nsort - j : 1;
-    const int mb_last = j < nsort ? m : mj;
-    launch_pack_diag(s, A, lda, j0, m, mb_last, cnt, d_pack);
-    if (hipMemcpyAsync(h_pack, d_pack, static_cast<size_t>(cnt) * mm * sizeof(double), hipMemcpyDeviceToHost, s) !=
-            hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return fail(TLRQMC_EDEVICE, "copy of the diagonal blocks failed");
-    std::vector<double> score(cnt);
-    std::vector<std::vector<int>> order(cnt);
-    std::vector<std::vector<double>> ymean(cnt);
-#pragma omp parallel for schedule(dynamic, 1)
-    for (int l = 0; l < cnt; ++l) {
-      std::vector<double> S, la(al.begin() + j0 + static_cast<int64_t>(l) * m,
-                                al.begin() + j0 + static_cast<int64_t>(l) * m + mb_last),
-          lb(bl.begin() + j0 + static_cast<int64_t>(l) * m, bl.begin() + j0 + static_cast<int64_t>(l) * m + mb_last);
-      sym_block(h_pack + static_cast<int64_t>(l) * mm, mb_last, S);
-      score[l] = univariate_conditioning(mb_last, S, la, lb, order[l], &ymean[l]);
-    }
-    int t = 0;
-    for (int l = 1; l < cnt; ++l)
-      if (score[l] < score[t]) t = l;
-    // positions j0.. take the chosen block (in its univariate-conditioning
-    // order) first; the block it displaces moves to the chosen one's place
-    rows.clear();
-    for (int u = 0; u < mj; ++u) {
-      src[j0 + u] = static_cast<int32_t>(j0 + static_cast<int64_t>(t) * m + order[t][u]);
-      rows.push_back(static_cast<int32_t>(j0 + u));
-    }
-    if (t != 0)
-      for (int u = 0; u < m; ++u) {
-        const int64_t q = j0 + static_cast<int64_t>(t) * m + u;
-        src[q] = static_cast<int32_t>(j0 + u);
-        rows.push_back(static_cast<int32_t>(q));
-      }
-    bool moved = false;
-    for (int32_t q : rows) moved = moved || src[q] != q;
-    if (moved) {
-      for (size_t k = 0; k < rows.size(); ++k) slot[rows[k]] = static_cast<int32_t>(k);
-      if (hipMemcpyAsync(d_rows, rows.data(), rows.size() * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
-          hipMemcpyAsync(d_src, src.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
-          hipMemcpyAsync(d_slot, slot.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess)
-        return fail(TLRQMC_EDEVICE, "copy of the reordering failed");
-      launch_permute_rows(s, A, lda, n, j0, static_cast<int>(rows.size()), d_rows, d_src, d_slot, d_tmp);
-      if (hipStreamSynchronize(s) != hipSuccess) return fail(TLRQMC_EDEVICE, "reordering kernel failed");
-      std::vector<int32_t> np(rows.size());
-      std::vector<double> na(rows.size()), nb(rows.size());
-      for (size_t k = 0; k < rows.size(); ++k) {
-        np[k] = p[src[rows[k]]];
-        na[k] = al[src[rows[k]]];
-        nb[k] = bl[src[rows[k]]];
-      }
-      for (size_t k = 0; k < rows.size(); ++k) {
-        p[rows[k]] = np[k];
-        al[rows[k]] = na[k];
-        bl[rows[k]] = nb[k];
-      }
-      for (int32_t q : rows) {
-        src[q] = q;
-        slot[q] = -1;
-      }
-    }
-    // factor the block, solve the panel below, condition the later limits
-    // on the block's truncated means, update the Schur complement
-    double *Ajj = A + j0 * lda + j0;
-    if ((st = device_potrf(ctx, h, mj, Ajj, lda, j0, m))) return st;
-    const int64_t rest = n - j0 - mj;
-    if (rest > 0) {
-      const double one = 1.0, zero = 0.0, minus = -1.0;
-      double *P = Ajj + mj;
-      if (hipMemcpyAsync(d_y, ymean[t].data(), mj * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
-        return fail(TLRQMC_EDEVICE, "copy failed");
-      std::lock_guard<std::mutex> g(g_blas_mutex);
-      if (rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
-                        rocblas_diagonal_non_unit, static_cast<rocblas_int>(rest), mj, &one, Ajj,
-                        static_cast<rocblas_int>(lda), P, static_cast<rocblas_int>(lda)) != rocblas_status_success ||
-          rocblas_dgemv(h, rocblas_operation_none, static_cast<rocblas_int>(rest), mj, &one, P,
-                        static_cast<rocblas_int>(lda), d_y, 1, &zero, d_t, 1) != rocblas_status_success ||
-          rocblas_dsyrk(h, rocblas_fill_lower, rocblas_operation_none, static_cast<rocblas_int>(rest), mj, &minus, P,
-                        static_cast<rocblas_int>(lda), &one, Ajj + mj * lda + mj,
-                        static_cast<rocblas_int>(lda)) != rocblas_status_success)
-        return fail(TLRQMC_EDEVICE, "rocBLAS update failed");
-      if (hipMemcpyAsync(tvec.data(), d_t, rest * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
-          hipStreamSynchronize(s) != hipSuccess)
-        return fail(TLRQMC_EDEVICE, "copy of the limit update failed");
-      for (int64_t i = 0; i < rest; ++i) {
-        al[j0 + mj + i] -= tvec[i];
-        bl[j0 + mj + i] -= tvec[i];
-      }
-    }
-  }
+  if ((st = rbodr_eliminate(ctx, h, A, lda, n, m, p, al, bl))) return st;
   phase[0] = secs(t_begin, clk::now());
   if (perm_out) std::copy(p.begin(), p.end(), perm_out);
   return compress_build(ctx, A, lda, n, m, p, tol, max_rank, phase, Aguard, out);

@@ -61,6 +61,17 @@ class Result(C.Structure):
                 ("kernel_busy_seconds", C.c_double * 5), ("kernel_launches", C.c_int64 * 5), ("n_shifts", C.c_int32), ("chunks", C.c_int32)]
 
 
+class SkewNormalParams(C.Structure):
+    _fields_ = [("xi", C.c_double), ("sigma1", C.c_double), ("beta1", C.c_double), ("sigma2", C.c_double),
+                ("beta2", C.c_double)]
+
+
+class SkewNormalResult(C.Structure):
+    _fields_ = [("loglik", C.c_double), ("log_density", C.c_double), ("log_prob", C.c_double),
+                ("log_prob_std_err", C.c_double), ("log_prob_rel_err", C.c_double), ("seconds", C.c_double * 3),
+                ("prob", Result)]
+
+
 class Request(C.Structure):
     _fields_ = [("n", C.c_int64), ("cov", Cov), ("a", C.c_void_p), ("b", C.c_void_p), ("nu", C.c_double),
                 ("m", C.c_int32), ("max_rank", C.c_int32), ("tol", C.c_double), ("reorder", C.c_int32),
@@ -106,6 +117,9 @@ SIGNATURES = {
                            C.POINTER(Result)]),
     "tlrqmc_sample_logp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                                      C.POINTER(QmcOpts), C.c_int32, C.c_int64, C.c_int64, C.c_void_p]),
+    "tlrqmc_skewnormal_loglik": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.POINTER(SkewNormalParams),
+                                           C.c_int, C.c_double, C.c_int, C.c_int, C.POINTER(QmcOpts),
+                                           C.POINTER(SkewNormalResult), C.c_void_p, C.POINTER(C.c_void_p)]),
     "tlrqmc_server_create": (C.c_int, [C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)]),
     "tlrqmc_server_submit": (C.c_int, [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_uint64)]),
     "tlrqmc_server_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int32, C.POINTER(Result), C.POINTER(RequestInfo)]),
@@ -389,6 +403,32 @@ def sample_logp(ctx: Context, factor: Factor, a, b, nu: float, N: int, M: int, s
     o = _opts(N, M, seed, precision, None, False, chunk)
     _check(lib().tlrqmc_sample_logp(ctx.handle, factor.handle, a.ctypes.data, b.ctypes.data, float(nu),
                                     C.byref(o), int(shift), int(k0), int(count), out.ctypes.data))
+    return out
+
+
+def skewnormal_loglik(ctx: Context, xy, z, xi: float, sigma1: float, beta1: float, sigma2: float, beta2: float,
+                      N: int, M: int, seed: int, m: int = 128, tol: float = 1e-5, max_rank: int = 0,
+                      order: int = 0, precision: int = 0, return_factor: bool = False) -> dict:
+    """Skew-normal log-likelihood (Eq. 6) of observations z at locations xy;
+    order 0 = geometric, 2 = block reordering during the Cholesky factorization."""
+    xy, z = _f64(xy), _f64(z)
+    n = len(z)
+    if xy.shape != (n, 2):
+        raise ValueError(f"xy must be {n} x 2")
+    prm = SkewNormalParams(float(xi), float(sigma1), float(beta1), float(sigma2), float(beta2))
+    o = _opts(N, M, seed, precision, None, False, 0)
+    res = SkewNormalResult()
+    c = np.empty(n)
+    h = C.c_void_p()
+    st = _check(lib().tlrqmc_skewnormal_loglik(ctx.handle, n, xy.ctypes.data, z.ctypes.data, C.byref(prm), int(m),
+                                               float(tol), int(max_rank), int(order), C.byref(o), C.byref(res),
+                                               c.ctypes.data, C.byref(h) if return_factor else None))
+    out = {"loglik": res.loglik, "log_density": res.log_density, "log_prob": res.log_prob,
+           "log_prob_std_err": res.log_prob_std_err, "log_prob_rel_err": res.log_prob_rel_err,
+           "seconds": {"linear_algebra": res.seconds[0], "factor": res.seconds[1], "estimate": res.seconds[2]},
+           "c": c, "prob": _result(res.prob, st)}
+    if return_factor:
+        out["factor"] = Factor(ctx, h)
     return out
 
 
