@@ -330,59 +330,88 @@ __device__ __forceinline__ float half_erfcx32(float z) {
   return (0.5f * 0.56418958354775628f) * r * sr;
 }
 
+// Phi^-1(exp(lu)) deep in the lower tail (exp(lu) < 1e-36), in FP64 with
+// few live values: there 1 - u = 1 to double precision, w' = -log 4 - lu
+// >= 81, and Phi^-1 = -sqrt2 p(w') with p in sqrt(w') (the last two tail
+// intervals of the FP64 table) up to w' = 756.25; further out, Newton steps
+// on log Phi from the asymptotic start.
+__device__ __noinline__ double Phi_inv_log_deep(double lu) {
+  ctab_t T = special_table();
+  const double wv = -kLog4 - lu;
+  if (wv <= 756.25) {
+    const double s = sqrt(wv);
+    const double pw = s < 14.0 ? horner<kOffInv4, kNInv4>(T, (s - kInvC4) * kInvH4)
+                               : horner<kOffInv5, kNInv5>(T, (s - kInvC5) * kInvH5);
+    return -M_SQRT2 * pw;
+  }
+  double y = -sqrt(-2.0 * lu - log_pos(T, -4.0 * M_PI * lu));
+  for (int it = 0; it < 12; ++it) {
+    const double z = -y * M_SQRT1_2;
+    const double lp = log_pos(T, 0.5 * erfcx_large(z)) - z * z;
+    const double dy = (lp - lu) / exp_nonpos(T, -z * z - kLogSqrt2Pi - lp);
+    y -= dy;
+    if (fabs(dy) <= 1e-16 * fabs(y)) break;
+  }
+  return y;
+}
+
 // Precision form of the one-sided step: Phi(bh), log Phi(bh) and the
 // quantile with FP32 special functions, FP64 where precision is made.
 //   q = Phi(-|bh|) = erfcx(|bh|/sqrt2) exp(-bh^2/2) / 2: erfcx in FP32, the
 //     exponent bh^2/2 split exactly in FP64 and reduced to 2^-(k + f) there.
-//   log Phi(bh) = log(erfcx/2) - bh^2/2 below zero (FP32 log, FP64 sum), and
-//     log1p(-q) = -2 atanh(q / (2 - q)) above (FP32 series).
+//   log Phi(bh) = log(erfcx/2) - bh^2/2 below zero (FP32 log, FP64 sum: valid
+//     however far out), and log1p(-q) = -2 atanh(q / (2 - q)) above (FP32
+//     series).
 //   u = w Phi(bh) and its complement c = 1 - u are formed in FP64 without
 //     cancellation (c = (1 - w) + w q above zero), and
 //     Phi^-1(u) = sqrt2 (u - c) p(w'), w' = -log(4 p (1 - p)), p = min(u, c),
 //     with p(w') in FP32 out to w' = 90 (p down to 1e-36).
-// Rows outside (bh < -13.1 where q leaves the FP32 range, infinite limits,
-// p < 1e-36) take the FP64 step.  The FP32 parts carry about 2e-7 relative
-// error; the running sum of log P stays FP64.
+//   Below p = 1e-36 (only where bh < 0) the quantile is taken in FP64 from
+//     log u = log w + log Phi(bh) (Phi_inv_log_deep).
+// The FP32 parts carry about 2e-7 relative error; the running sum of log P
+// stays FP64.
 __device__ inline double sov_step_upper_fp32(double bh, double w, double &y) {
   constexpr float kLn2f = 0.69314718055994531f;
-  if (bh >= -13.1 && bh < INFINITY) {
-    const double ab = fabs(bh);
-    const float ex = half_erfcx32(static_cast<float>(ab * M_SQRT1_2));
-    const double p2 = bh * bh;
-    const double a = 0.5 * p2;
-    const double al = 0.5 * fma(bh, bh, -p2);  // bh^2 / 2 = a + al exactly
-    const double tt = (a + al) * M_LOG2E;
-    const double kf = floor(tt);
-    const float q = __builtin_amdgcn_ldexpf(ex * __builtin_amdgcn_exp2f(-static_cast<float>(tt - kf)),
-                                             -static_cast<int>(kf));
-    const double qd = static_cast<double>(q);
-    const bool neg = bh < 0.0;
-    // log Phi(bh): both forms are cheap, the sign selects
-    const double l_neg = static_cast<double>(__builtin_amdgcn_logf(ex) * kLn2f) - a - al;
-    const float v = q * __builtin_amdgcn_rcpf(2.0f - q);
-    const float v2 = v * v;
-    const float at = fmaf(fmaf(fmaf(fmaf(fmaf(fmaf(fmaf(1.0f / 15.0f, v2, 1.0f / 13.0f), v2, 1.0f / 11.0f), v2,
-                                              1.0f / 9.0f), v2, 1.0f / 7.0f), v2, 0.2f), v2, 1.0f / 3.0f), v2, 1.0f);
-    const double le = neg ? l_neg : static_cast<double>(-2.0f * v * at);
-    const double u = neg ? w * qd : fma(-w, qd, w);
-    const double c = neg ? 1.0 - u : fma(w, qd, 1.0 - w);
-    const double pm = fmin(u, c);
-    if (pm >= 1e-36) {
-      const float pf = static_cast<float>(pm);
-      const float wv = -__builtin_amdgcn_logf(4.0f * pf * (1.0f - pf)) * kLn2f;
-      float pw;
-      if (wv < 6.25f) {
-        pw = horner32(kInv32, (wv - kInv32C) * kInv32H);
-      } else {
-        const float sq = __builtin_amdgcn_sqrtf(wv);
-        pw = sq < kInv32Split ? horner32(kInv32T0, (sq - kInv32T0C) * kInv32T0H)
-                              : horner32(kInv32T1, (sq - kInv32T1C) * kInv32T1H);
-      }
-      y = M_SQRT2 * (u - c) * static_cast<double>(pw);
-      return le;
-    }
+  if (bh == -INFINITY) {  // an empty interval: a dead sample
+    y = 0.0;
+    return -INFINITY;
   }
-  return sov_step_upper(bh, w, y);
+  const double ab = fabs(bh);
+  const float ex = half_erfcx32(static_cast<float>(ab * M_SQRT1_2));
+  const double p2 = bh * bh;
+  const double a = 0.5 * p2;
+  const double al = isinf(bh) ? 0.0 : 0.5 * fma(bh, bh, -p2);  // bh^2 / 2 = a + al exactly
+  const double tt = fmin((a + al) * M_LOG2E, 200.0);
+  const double kf = floor(tt);
+  const float q = __builtin_amdgcn_ldexpf(ex * __builtin_amdgcn_exp2f(-static_cast<float>(tt - kf)),
+                                           -static_cast<int>(kf));
+  const double qd = static_cast<double>(q);
+  const bool neg = bh < 0.0;
+  const double l_neg = static_cast<double>(__builtin_amdgcn_logf(ex) * kLn2f) - a - al;
+  const float v = q * __builtin_amdgcn_rcpf(2.0f - q);
+  const float v2 = v * v;
+  const float at = fmaf(fmaf(fmaf(fmaf(fmaf(fmaf(fmaf(1.0f / 15.0f, v2, 1.0f / 13.0f), v2, 1.0f / 11.0f), v2,
+                                            1.0f / 9.0f), v2, 1.0f / 7.0f), v2, 0.2f), v2, 1.0f / 3.0f), v2, 1.0f);
+  const double le = neg ? l_neg : static_cast<double>(-2.0f * v * at);
+  const double u = neg ? w * qd : fma(-w, qd, w);
+  const double c = neg ? 1.0 - u : fma(w, qd, 1.0 - w);
+  const double pm = fmin(u, c);
+  if (pm >= 1e-36) {
+    const float pf = static_cast<float>(pm);
+    const float wv = -__builtin_amdgcn_logf(4.0f * pf * (1.0f - pf)) * kLn2f;
+    float pw;
+    if (wv < 6.25f) {
+      pw = horner32(kInv32, (wv - kInv32C) * kInv32H);
+    } else {
+      const float sq = __builtin_amdgcn_sqrtf(wv);
+      pw = sq < kInv32Split ? horner32(kInv32T0, (sq - kInv32T0C) * kInv32T0H)
+                            : horner32(kInv32T1, (sq - kInv32T1C) * kInv32T1H);
+    }
+    y = M_SQRT2 * (u - c) * static_cast<double>(pw);
+  } else {
+    y = Phi_inv_log_deep(log_pos(special_table(), w) + le);
+  }
+  return le;
 }
 
 // Regularized incomplete gamma: returns P(a, x) and sets q = Q(a, x).

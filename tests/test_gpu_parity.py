@@ -170,17 +170,18 @@ def test_orthant_probability_tlr(T, ctx):
     assert abs(res["p"] - 1.0 / (n + 1)) <= 3.0 * res["std_err"]
 
 
-def test_empty_interval_and_infinite_limits(T, ctx):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_empty_interval_and_infinite_limits(T, ctx, precision):
     n, m = 100, 32
     fac = synth.random_tlr_factor(n, m, seed=2)
     F = T.Factor.from_tiles(ctx, n, m, *fac)
     a = np.full(n, -np.inf)
     b = np.full(n, 1.0)
     b[7] = -np.inf
-    res = T.probability(ctx, F, a, b, 100, 2, 1)
+    res = T.probability(ctx, F, a, b, 100, 2, 1, precision=precision)
     assert res["log_p"] == -np.inf and res["p"] == 0.0
     b = np.full(n, np.inf)
-    res = T.probability(ctx, F, a, b, 100, 2, 1, return_logp=True)
+    res = T.probability(ctx, F, a, b, 100, 2, 1, precision=precision, return_logp=True)
     assert res["log_p"] == 0.0 and np.all(res["logp"] == 0.0)
 
 
@@ -277,6 +278,35 @@ def test_precision_form_within_standard_error(T, ctx, case):
     print(f"{case}: max per-sample scaled error {err.max():.2e}, "
           f"|dP|/SE = {abs(res['p'] - ref['p']) / ref['std_err']:.2e}")
     assert err.max() <= 1e-3
+
+
+def test_precision_form_deep_lower_tail(T, ctx):
+    """One-sided limits far into the lower tail (Phi(bh) down to 1e-440):
+    the precision form takes log Phi from the FP32 erfcx at any depth and the
+    quantile of u < 1e-36 in FP64 (tail polynomial, then Newton beyond
+    w' = 756).  Neighbour correlation 0.1 carries each quantile into the next
+    limit.  Per sample: the FP64 form within 1e-10 of the oracle; the
+    precision form within 1e-7 max(1, |log P|), about 3e-3 absolute at
+    |log P| ~ 27,000, against 150 variables x 1.5e-5 (2e-7 relative error of
+    the FP32 Phi, plus a quantile error of 2e-7 |y| carried into a limit
+    where d log Phi / d bh ~ 45)."""
+    n, m = 150, 64
+    x = np.arange(n, dtype=np.float64)
+    L = np.linalg.cholesky(np.exp(-np.abs(x[:, None] - x[None, :]) / 0.4343))
+    fac = OF.tlr_from_dense(L, m, 1e-15)[:4]
+    targets = np.array([-45.0, -38.0, -30.0, -20.0, -13.5, -12.5, -9.0, -5.0, -1.0, 0.0, 2.0, 40.0, np.inf])
+    b = np.diag(L) * targets[np.arange(n) % len(targets)]
+    a = np.full(n, -np.inf)
+    perm = np.arange(n, dtype=np.int32)
+    N, M, seed = 640, 3, 9
+    ref, ref_logp = oracle.probability(fac, a, b, 0.0, N, M, seed)
+    assert np.all(np.isfinite(ref_logp)) and ref_logp.max() < -2000.0
+    F = T.Factor.from_tiles(ctx, n, m, fac[0], fac[1], fac[2], fac[3], perm)
+    for precision, tol in ((0, TOL), (1, 1e-7)):
+        res = T.probability(ctx, F, a, b, N, M, seed, precision=precision, return_logp=True)
+        err = np.abs(res["logp"] - ref_logp) / np.maximum(1.0, np.abs(ref_logp))
+        print(f"precision {precision}: max per-sample scaled error {err.max():.2e}")
+        assert_logp_close(res["logp"], ref_logp, tol)
 
 
 def test_precision_form_matches_fp64_form(T, ctx):
