@@ -304,8 +304,9 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
         }
         SweepParams sp{g0 + c0, cnt, N, ld, n + 1, f->tm[j], static_cast<int>(1 + f->toff[j]),
                        f->d_diag + f->diag_off[j], two_sided ? d_a + f->toff[j] : nullptr,
-                       d_b + f->toff[j], (has_delta && !prec) ? L.Dl : nullptr,
-                       (has_delta && prec) ? L.DlF : nullptr, L.R, f->d_gen, d_D, d_logp + c0, L.Y};
+                       d_b + f->toff[j],
+                       has_delta ? (prec ? static_cast<const void *>(L.DlF) : static_cast<const void *>(L.Dl)) : nullptr,
+                       L.R, f->d_gen, d_D, d_logp + c0, L.Y};
         prof.begin(TLRQMC_KERNEL_SWEEP, L.s);
         launch_sweep(L.s, sp, two_sided, nu > 0, prec);
         prof.end(L.s);

@@ -34,6 +34,14 @@ __device__ __forceinline__ const TLRQMC_CONST T *as_const(const T *p) {
   return (const TLRQMC_CONST T *)p;
 }
 
+// A pointer into global memory, marked so: loads through it are global
+// loads (counted on the vector memory counter only) rather than flat ones.
+#define TLRQMC_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const TLRQMC_GLOBAL T *as_global(const T *p) {
+  return (const TLRQMC_GLOBAL T *)p;
+}
+
 // Copy of a wave-uniform descriptor in device memory, read with scalar
 // loads (T is a plain struct of 8-byte multiples).
 template <class T>

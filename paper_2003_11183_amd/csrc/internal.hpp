@@ -180,8 +180,7 @@ struct SweepParams {
   int mj, c0;              // rows of the tile, lattice coordinate of row 0
   const double *B;         // blocked tile
   const double *a, *b;     // limits of the tile rows (a unused when one-sided)
-  const double *Delta;     // m x ld low-rank update, or null
-  const float *DeltaF;     // the same in FP32 (precision form), or null
+  const void *Delta;       // m x ld low-rank update (FP32 in the precision form, FP64 otherwise), or null
   const double *R;         // per chunk sample, or null
   const uint64_t *A, *D;
   double *logp;            // per chunk sample
@@ -224,7 +223,7 @@ int lr_mfma_rt(int rows);
 int64_t lr_mfma_rows(int rows);
 void launch_lr_mfma(hipStream_t s, const MfmaLrParams &p);
 void launch_init(hipStream_t s, const InitParams &p);
-void launch_sweep(hipStream_t s, const SweepParams &p, bool two_sided, bool scaled, bool mixed);
+void launch_sweep(hipStream_t s, const SweepParams &p, bool two_sided, bool scaled, bool prec);
 void launch_delta_f64(hipStream_t s, const LrParams &p);
 void launch_zproj_f64(hipStream_t s, const LrParams &p);
 void launch_reduce(hipStream_t s, const ReduceParams &p, int n_shifts);
@@ -233,7 +232,7 @@ void launch_reduce(hipStream_t s, const ReduceParams &p, int n_shifts);
 // launch is the one its descriptor would make alone.
 void launch_init_batch(hipStream_t s, const InitParams *d, int n, int64_t max_count);
 void launch_sweep_batch(hipStream_t s, const SweepParams *d, int n, int64_t max_count, bool two_sided, bool scaled,
-                        bool mixed);
+                        bool prec);
 void launch_delta_f64_batch(hipStream_t s, const LrParams *d, int n, int64_t max_count, int max_rows);
 void launch_zproj_f64_batch(hipStream_t s, const LrParams *d, int n, int64_t max_count, int max_rows);
 void launch_reduce_batch(hipStream_t s, const ReduceParams *d, int n, int max_shifts);

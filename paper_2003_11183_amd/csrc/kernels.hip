@@ -12,6 +12,8 @@
 //   k_sweep     : the SOV recursion over the rows of B_j (Section 2.1, Eq. 2)
 //   k_zproj_f64 : Z(:, j) = V_panel(j)^T Y_j    (rank-space image of y_j)
 // and k_reduce combines log P per shift (Section 2.1: mean over samples).
+#include <type_traits>
+
 #include "device_math.hpp"
 #include "internal.hpp"
 
@@ -59,10 +61,35 @@ __global__ __launch_bounds__(256) void k_init_batch(const InitParams *ps) {
 // Within a row block the recursion is right looking: acc[i] holds the
 // partial row sum of row t + i; after y_t is known the column below the
 // diagonal is added and the window slides down by one, so every index into
-// acc is a compile-time constant and acc stays in registers.
-template <bool TWO_SIDED, bool SCALED, bool MIXED>
+// acc is a compile-time constant and acc stays in registers.  (Unrolling the
+// sixteen rows instead, which would update only the triangle, measured half
+// as fast.)
+//
+// The per-lane operands of a row (shift word, low-rank update) are loaded
+// one row ahead and converted only when used, so that their memory latency
+// overlaps the previous row's special functions.  The load is unconditional:
+// a tile without a low-rank update reads a zero with zero strides.
+//
+// PREC selects the precision form: the low-rank update arrives in FP32 and
+// the one-sided step takes its special functions in FP32.
+__device__ const double kNoDelta64 = 0.0;
+__device__ const float kNoDelta32 = 0.0f;
+
+template <class DT>
+struct RowOperands {
+  uint64_t d;
+  DT dl;
+};
+
+template <class DT>
+__device__ __forceinline__ RowOperands<DT> row_operands(const uint64_t *Ds, const DT *Dl, int64_t dls, int row) {
+  return RowOperands<DT>{as_global(Ds)[row], as_global(Dl)[row * dls]};
+}
+
+template <bool TWO_SIDED, bool SCALED, bool PREC>
 __device__ __forceinline__ void sweep_body(const SweepParams &p, int64_t si) {
   constexpr int SB = kSweepBlock;
+  using DT = typename std::conditional<PREC, float, double>::type;
   if (si >= p.count) return;
   const int64_t g = p.g0 + si;
   const int64_t s = g / p.N;
@@ -74,8 +101,11 @@ __device__ __forceinline__ void sweep_body(const SweepParams &p, int64_t si) {
   const double R = SCALED ? p.R[si] : 1.0;
   const int64_t ld = p.ld;
   double *Y = p.Y + si;
-  const double *Dl = p.Delta ? p.Delta + si : nullptr;
-  const float *DlF = p.DeltaF ? p.DeltaF + si : nullptr;
+  const bool has_delta = p.Delta != nullptr;
+  const DT *Dl = has_delta ? static_cast<const DT *>(p.Delta) + si
+                           : (PREC ? reinterpret_cast<const DT *>(&kNoDelta32)
+                                   : reinterpret_cast<const DT *>(&kNoDelta64));
+  const int64_t dls = has_delta ? ld : 0;
   double lp = p.logp[si];
   const int nb = (p.mj + SB - 1) / SB;
   auto blk = as_const(p.B);
@@ -93,50 +123,61 @@ __device__ __forceinline__ void sweep_body(const SweepParams &p, int64_t si) {
       }
     }
     const int rows = min(SB, p.mj - q * SB);
-    // Per-lane operands of the next row (shift word, low-rank update) are
-    // loaded one row ahead so that their memory latency overlaps the
-    // current row's special functions.
-    int row = q * SB;
-    uint64_t dnext = Ds[row];
-    double dlnext = Dl ? Dl[row * ld] : (DlF ? static_cast<double>(DlF[row * ld]) : 0.0);
-    for (int t = 0; t < rows; ++t, ++row) {
-      const uint64_t dcur = dnext;
-      const double dlt = dlnext;
-      if (t + 1 < rows) {
-        dnext = Ds[row + 1];
-        dlnext = Dl ? Dl[(row + 1) * ld] : (DlF ? static_cast<double>(DlF[(row + 1) * ld]) : 0.0);
-      }
-      const auto col = blk + t * SB;
-      const double bt = R * bl[row] - dlt;
-      const double w = lattice_point(k, Ag[row], dcur);
-      double y, ldel;
-      if (TWO_SIDED) {
-        const double at = R * al[row] - dlt;
-        ldel = sov_step((at - acc[0]) * col[0], (bt - acc[0]) * col[0], w, y);
-      } else {
-        ldel = MIXED ? sov_step_upper_fp32((bt - acc[0]) * col[0], w, y)
-                     : sov_step_upper((bt - acc[0]) * col[0], w, y);
-      }
-      lp += ldel;
-      Y[row * ld] = y;
+    const int r0 = q * SB;
+    RowOperands<DT> nxt = row_operands(Ds, Dl, dls, r0);
+    {
+      // wave-uniform operands (limit, inverse diagonal, generator) of the
+      // next row are fetched one row ahead, and the column below the
+      // diagonal before the special functions that precede its use
+      double bn = bl[r0], an = TWO_SIDED ? al[r0] : 0.0, dn = blk[0];
+      uint64_t gn = Ag[r0];
+      for (int t = 0; t < rows; ++t) {
+        const int row = r0 + t;
+        const RowOperands<DT> cur = nxt;
+        const double bc = bn, ac = an, dinv = dn;
+        const uint64_t gc = gn;
+        const auto col = blk + t * SB;
+        double c[SB - 1];
 #pragma unroll
-      for (int i = 1; i < SB; ++i) acc[i - 1] = fma(col[i], y, acc[i]);
-      acc[SB - 1] = 0.0;
+        for (int i = 1; i < SB; ++i) c[i - 1] = col[i];
+        if (t + 1 < rows) {
+          nxt = row_operands(Ds, Dl, dls, row + 1);
+          bn = bl[row + 1];
+          if (TWO_SIDED) an = al[row + 1];
+          dn = col[SB];
+          gn = Ag[row + 1];
+        }
+        const double dl = static_cast<double>(cur.dl);
+        const double bt = R * bc - dl;
+        const double w = lattice_point(k, gc, cur.d);
+        double y;
+        if constexpr (TWO_SIDED) {
+          const double at = R * ac - dl;
+          lp += sov_step((at - acc[0]) * dinv, (bt - acc[0]) * dinv, w, y);
+        } else {
+          lp += PREC ? sov_step_upper_fp32((bt - acc[0]) * dinv, w, y)
+                     : sov_step_upper((bt - acc[0]) * dinv, w, y);
+        }
+        Y[row * ld] = y;
+#pragma unroll
+        for (int i = 1; i < SB; ++i) acc[i - 1] = fma(c[i - 1], y, acc[i]);
+        acc[SB - 1] = 0.0;
+      }
     }
     blk += SB * SB;
   }
   p.logp[si] = lp;
 }
 
-template <bool TWO_SIDED, bool SCALED, bool MIXED>
+template <bool TWO_SIDED, bool SCALED, bool PREC>
 __global__ __launch_bounds__(256) void k_sweep(SweepParams p) {
-  sweep_body<TWO_SIDED, SCALED, MIXED>(p, static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x);
+  sweep_body<TWO_SIDED, SCALED, PREC>(p, static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x);
 }
 
-template <bool TWO_SIDED, bool SCALED, bool MIXED>
+template <bool TWO_SIDED, bool SCALED, bool PREC>
 __global__ __launch_bounds__(256) void k_sweep_batch(const SweepParams *ps) {
   const SweepParams p = load_uniform(ps + blockIdx.y);
-  sweep_body<TWO_SIDED, SCALED, MIXED>(p, static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x);
+  sweep_body<TWO_SIDED, SCALED, PREC>(p, static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x);
 }
 
 // ------------------------------------------------------- low rank, FP64 ----
@@ -272,17 +313,20 @@ void launch_init(hipStream_t s, const InitParams &p) {
   hipLaunchKernelGGL(k_init, dim3(grid_of(p.count)), dim3(256), 0, s, p);
 }
 
-void launch_sweep(hipStream_t s, const SweepParams &p, bool two_sided, bool scaled, bool mixed) {
-  const dim3 grid(grid_of(p.count)), block(256);
+template <bool TWO_SIDED, bool SCALED>
+static void sweep_form(hipStream_t s, const SweepParams &p, dim3 grid, bool prec) {
+  if (prec) hipLaunchKernelGGL((k_sweep<TWO_SIDED, SCALED, true>), grid, dim3(256), 0, s, p);
+  else hipLaunchKernelGGL((k_sweep<TWO_SIDED, SCALED, false>), grid, dim3(256), 0, s, p);
+}
+
+void launch_sweep(hipStream_t s, const SweepParams &p, bool two_sided, bool scaled, bool prec) {
+  const dim3 grid(grid_of(p.count));
   if (two_sided) {
-    if (scaled) hipLaunchKernelGGL((k_sweep<true, true, false>), grid, block, 0, s, p);
-    else hipLaunchKernelGGL((k_sweep<true, false, false>), grid, block, 0, s, p);
-  } else if (mixed) {
-    if (scaled) hipLaunchKernelGGL((k_sweep<false, true, true>), grid, block, 0, s, p);
-    else hipLaunchKernelGGL((k_sweep<false, false, true>), grid, block, 0, s, p);
+    if (scaled) sweep_form<true, true>(s, p, grid, prec);
+    else sweep_form<true, false>(s, p, grid, prec);
   } else {
-    if (scaled) hipLaunchKernelGGL((k_sweep<false, true, false>), grid, block, 0, s, p);
-    else hipLaunchKernelGGL((k_sweep<false, false, false>), grid, block, 0, s, p);
+    if (scaled) sweep_form<false, true>(s, p, grid, prec);
+    else sweep_form<false, false>(s, p, grid, prec);
   }
 }
 
@@ -304,18 +348,21 @@ void launch_init_batch(hipStream_t s, const InitParams *d, int n, int64_t max_co
   hipLaunchKernelGGL(k_init_batch, dim3(grid_of(max_count), n), dim3(256), 0, s, d);
 }
 
+template <bool TWO_SIDED, bool SCALED>
+static void sweep_batch_form(hipStream_t s, const SweepParams *d, dim3 grid, bool prec) {
+  if (prec) hipLaunchKernelGGL((k_sweep_batch<TWO_SIDED, SCALED, true>), grid, dim3(256), 0, s, d);
+  else hipLaunchKernelGGL((k_sweep_batch<TWO_SIDED, SCALED, false>), grid, dim3(256), 0, s, d);
+}
+
 void launch_sweep_batch(hipStream_t s, const SweepParams *d, int n, int64_t max_count, bool two_sided, bool scaled,
-                        bool mixed) {
-  const dim3 grid(grid_of(max_count), n), block(256);
+                        bool prec) {
+  const dim3 grid(grid_of(max_count), n);
   if (two_sided) {
-    if (scaled) hipLaunchKernelGGL((k_sweep_batch<true, true, false>), grid, block, 0, s, d);
-    else hipLaunchKernelGGL((k_sweep_batch<true, false, false>), grid, block, 0, s, d);
-  } else if (mixed) {
-    if (scaled) hipLaunchKernelGGL((k_sweep_batch<false, true, true>), grid, block, 0, s, d);
-    else hipLaunchKernelGGL((k_sweep_batch<false, false, true>), grid, block, 0, s, d);
+    if (scaled) sweep_batch_form<true, true>(s, d, grid, prec);
+    else sweep_batch_form<true, false>(s, d, grid, prec);
   } else {
-    if (scaled) hipLaunchKernelGGL((k_sweep_batch<false, true, false>), grid, block, 0, s, d);
-    else hipLaunchKernelGGL((k_sweep_batch<false, false, false>), grid, block, 0, s, d);
+    if (scaled) sweep_batch_form<false, true>(s, d, grid, prec);
+    else sweep_batch_form<false, false>(s, d, grid, prec);
   }
 }
 

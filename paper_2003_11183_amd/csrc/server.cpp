@@ -172,7 +172,7 @@ struct StepBatch {
   std::vector<LrParams> f64[2];        // [delta, projection]
   int64_t f64_max[2] = {};
   int f64_rows[2] = {};
-  std::vector<SweepParams> sweep[8];   // two_sided * 4 + scaled * 2 + mixed
+  std::vector<SweepParams> sweep[8];   // two_sided * 4 + scaled * 2 + prec
   int64_t sweep_max[8] = {};
   std::vector<ReduceParams> reduce;
   int reduce_max = 0;
@@ -534,12 +534,14 @@ int tlrqmc_server::step(StepBatch &B, int cur) {
         B.f64_rows[0] = std::max(B.f64_rows[0], f->tm[j]);
       }
     }
-    const int v = (q->two_sided ? 4 : 0) + (q->scaled ? 2 : 0) + (q->prec && !q->two_sided ? 1 : 0);
+    const int v = (q->two_sided ? 4 : 0) + (q->scaled ? 2 : 0) + (q->prec ? 1 : 0);
     B.sweep[v].push_back(SweepParams{s.c0, s.cnt, N, ld, n + 1, f->tm[j], static_cast<int>(1 + f->toff[j]),
                                      f->d_diag + f->diag_off[j], q->two_sided ? q->d_a + f->toff[j] : nullptr,
-                                     q->d_b + f->toff[j], (has_delta && !q->prec) ? s.Dl : nullptr,
-                                     (has_delta && q->prec) ? s.DlF : nullptr, s.R, f->d_gen, q->d_D,
-                                     q->d_logp + s.c0, s.Y});
+                                     q->d_b + f->toff[j],
+                                     has_delta ? (q->prec ? static_cast<const void *>(s.DlF)
+                                                          : static_cast<const void *>(s.Dl))
+                                               : nullptr,
+                                     s.R, f->d_gen, q->d_D, q->d_logp + s.c0, s.Y});
     B.sweep_max[v] = std::max(B.sweep_max[v], s.cnt);
     if (j < r - 1 && f->kcol[j] > 0) {
       if (q->prec) {
