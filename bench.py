@@ -32,7 +32,7 @@ METRIC = "QMC sample·dims/sec at n=16384 (FP64 vs BF16-MFMA); p50/p99 latency p
 PEAK_FP64_VALU = 78.6e12    # 256 CU x 2.4 GHz x 64 lanes x 2 flops (FMA)
 PEAK_BF16_MFMA = 2.5e15     # dense
 # FP64 operations per variable of the sweep beyond the row products (Phi, log,
-# Phi^-1, lattice point, bookkeeping); see the design doc section 5.
+# Phi^-1, lattice point, bookkeeping).
 C_PHI = 150
 
 
@@ -94,19 +94,21 @@ def time_form(T, ctx, F, c, precision, steps, warmup):
 # HBM bytes per launch of a kernel (FETCH_SIZE x fetch scale + WRITE_SIZE x
 # write scale, both scaled by what the counters read for a plain 1 GiB copy),
 # from the rocprofv3 runs summarised under profiles/.  A figure is reported
-# only while the kernel sources still have the digest it was measured on.
+# only while the kernel sources and the build script (its device flags) still
+# have the digest it was measured on.
 TRAFFIC = {
     (3, "sweep", 1): {"bytes_per_launch": 3.696e9, "digest": "4809b8c34cfea878"},
     (3, "delta", 0): {"bytes_per_launch": 2.177e9, "digest": "4809b8c34cfea878"},
 }
-KERNEL_SOURCES = ("kernels.hip", "kernels_mfma.hip", "device_math.hpp", "special_tables.hpp", "internal.hpp")
+KERNEL_SOURCES = tuple(os.path.join("csrc", f) for f in (
+    "kernels.hip", "kernels_mfma.hip", "device_math.hpp", "special_tables.hpp", "internal.hpp")) + ("build.py",)
 
 
 def kernel_digest() -> str:
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2003_11183_amd", "csrc", f), "rb") as fh:
+        with open(os.path.join(ROOT, "paper_2003_11183_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -144,7 +146,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+                                   "(sharding across GPUs is designed, not built)"}))
         sys.exit(2)
     import torch
     if args.copy_calibration > 0:

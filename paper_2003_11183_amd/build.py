@@ -32,6 +32,12 @@ DEVICE = [os.path.join(ROCM, "bin", "hipcc"), f"--offload-arch={ARCH}",
           "-mllvm", "-disable-machine-licm"] + COMMON
 
 
+# Per-file device options.  The low-rank MFMA kernels keep their
+# accumulators in ordinary VGPRs instead of AGPRs: the two share one register
+# file, and the VGPR form needs fewer registers in total (more waves).
+FILE_FLAGS = {"kernels_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def sources():
     return sorted(f for f in os.listdir(CSRC) if f.endswith((".cpp", ".hip")))
 
@@ -42,7 +48,8 @@ def build(verbose: bool = False) -> str:
     objs = []
     for src in sources():
         obj = os.path.join(BUILD, src + ".o")
-        cmd = (HOST if src.endswith(".cpp") else DEVICE) + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = (HOST if src.endswith(".cpp") else DEVICE + FILE_FLAGS.get(src, [])) + ["-c", os.path.join(CSRC, src),
+                                                                             "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))

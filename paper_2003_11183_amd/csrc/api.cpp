@@ -222,6 +222,7 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
   }
   chunk = round_up(std::min(chunk, count), 256);
   const int64_t ld = chunk;
+  SharedDevice dev;  // no library factorization runs beside these kernels
   Scratch sc(ctx);
   double *d_a = two_sided ? sc.get<double>(n) : nullptr;
   double *d_b = sc.get<double>(n);

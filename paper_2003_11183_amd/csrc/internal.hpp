@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <condition_variable>
 #include <cstdint>
 #include <mutex>
 #include <string>
@@ -140,12 +141,61 @@ T *Scratch::get(size_t count) {
 // Destroy a context's cached rocBLAS handle (setup.cpp).
 void release_blas(tlrqmc_ctx *ctx);
 
+// ---- device lock (setup.cpp) ----
+// rocSOLVER / rocBLAS factorizations returned wrong factors (errors of 0.1 in
+// entries of L, starting a few panels in) while this library's estimator
+// kernels ran beside them on other streams; on an idle device, or beside
+// other kernels that were tried, they are exact and reproducible.  So every
+// library factorization call runs with the device to itself: it holds this
+// lock exclusively, after draining the device, and every section of this
+// library that launches its own kernels holds it shared.  Writers are
+// preferred, so short shared sections cannot starve a factorization.  Shared
+// holds nest within a thread; an exclusive section entered while the thread
+// holds it shared gives that hold up for its duration (the drain completes
+// the thread's own work first).
+class DeviceLock {
+ public:
+  void lock_shared();
+  void unlock_shared();
+  void lock();
+  void unlock();
+
+ private:
+  std::mutex mu_;
+  std::condition_variable cv_;
+  int readers_ = 0, writers_waiting_ = 0;
+  bool writer_ = false;
+};
+DeviceLock &device_lock();
+
+// Scope holding the device lock shared (kernel launches of this library).
+class SharedDevice {
+ public:
+  SharedDevice();
+  ~SharedDevice();
+  SharedDevice(const SharedDevice &) = delete;
+  SharedDevice &operator=(const SharedDevice &) = delete;
+};
+
+// Scope holding the device lock exclusively with the device drained; `ok`
+// is false when the drain failed.  The scope's library calls must be
+// complete (their stream synchronized) before it ends.
+class ExclusiveDevice {
+ public:
+  ExclusiveDevice();
+  ~ExclusiveDevice();
+  ExclusiveDevice(const ExclusiveDevice &) = delete;
+  ExclusiveDevice &operator=(const ExclusiveDevice &) = delete;
+  bool ok = false;
+
+ private:
+  int held_shared_ = 0;
+};
+
 // ---- dense device linear algebra shared by the clients (setup.cpp) ----
-// The context's rocBLAS handle on its stream (rocblas_handle), and the lock
-// every rocSOLVER / rocBLAS factorization call of the library holds.
+// The context's rocBLAS handle on its stream (rocblas_handle).
 typedef struct _rocblas_handle *rocblas_handle_t;
 rocblas_handle_t blas_handle(tlrqmc_ctx *ctx);
-std::mutex &blas_mutex();
 // Cholesky (lower) of the n x n device matrix A in place; ENOTSPD names the column.
 int device_cholesky(tlrqmc_ctx *ctx, double *A, int64_t lda, int64_t n);
 // TLR factor of the symmetric device matrix S (lower stored, leading

@@ -72,6 +72,18 @@ __global__ __launch_bounds__(256) void k_init_batch(const InitParams *ps) {
 //
 // PREC selects the precision form: the low-rank update arrives in FP32 and
 // the one-sided step takes its special functions in FP32.
+//
+// Rows of earlier blocks enter through FP64 matrix cores: for row block q a
+// wave forms C(64 samples x 16 rows) = sum_{p<q} Y_p(64 x 16) B(q,p)^T with
+// v_mfma_f64_16x16x4_f64, four 16-sample tiles side by side.  The A operand
+// is y of this wave's samples (lane l: sample 16*tile + l%16, block column
+// 4*kstep + l/16), the B operand is the factor block read once per k-step
+// (lane l: entry [(4*kstep + l/16)*16 + l%16], contiguous).  The result
+// leaves the matrix layout through a wave-private LDS tile (two halves of
+// 32 samples) into the per-lane accumulator.  Every lane of a wave takes
+// part; lanes past the chunk's end compute on clamped indices and store
+// nothing outside their own Y column, which lies inside the leading
+// dimension.
 __device__ const double kNoDelta64 = 0.0;
 __device__ const float kNoDelta32 = 0.0f;
 
@@ -86,19 +98,32 @@ __device__ __forceinline__ RowOperands<DT> row_operands(const uint64_t *Ds, cons
   return RowOperands<DT>{as_global(Ds)[row], as_global(Dl)[row * dls]};
 }
 
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// Output layout of v_mfma_f64_16x16x4_f64: lane l holds column l % 16 and
+// rows l / 16 + 4 r of the 16 x 16 tile, r = 0..3.
+__device__ __forceinline__ int mfma64_row(int lane, int r) { return lane / 16 + 4 * r; }
+
+constexpr int kTrLd = 18;  // LDS row stride of the transposition (doubles)
+
 template <bool TWO_SIDED, bool SCALED, bool PREC>
-__device__ __forceinline__ void sweep_body(const SweepParams &p, int64_t si) {
+__device__ __forceinline__ void sweep_body(const SweepParams &p, int64_t si, double *tr) {
   constexpr int SB = kSweepBlock;
+  static_assert(SB == 16, "the matrix-core block products assume 16-row blocks");
   using DT = typename std::conditional<PREC, float, double>::type;
-  if (si >= p.count) return;
-  const int64_t g = p.g0 + si;
+  const int lane = static_cast<int>(threadIdx.x) & 63;
+  const int64_t w0 = si - lane;
+  if (w0 >= p.count) return;  // whole wave past the end
+  const bool live = si < p.count;
+  const int64_t sl = live ? si : p.count - 1;
+  const int64_t g = p.g0 + sl;
   const int64_t s = g / p.N;
   const uint64_t k = static_cast<uint64_t>(g - s * p.N) + 1;
   const uint64_t *Ds = p.D + s * p.ldD + p.c0;
   const auto Ag = as_const(p.A + p.c0);
   const auto bl = as_const(p.b);
   const auto al = as_const(p.a);
-  const double R = SCALED ? p.R[si] : 1.0;
+  const double R = SCALED ? p.R[sl] : 1.0;
   const int64_t ld = p.ld;
   double *Y = p.Y + si;
   const bool has_delta = p.Delta != nullptr;
@@ -106,20 +131,42 @@ __device__ __forceinline__ void sweep_body(const SweepParams &p, int64_t si) {
                            : (PREC ? reinterpret_cast<const DT *>(&kNoDelta32)
                                    : reinterpret_cast<const DT *>(&kNoDelta64));
   const int64_t dls = has_delta ? ld : 0;
-  double lp = p.logp[si];
+  double lp = p.logp[sl];
   const int nb = (p.mj + SB - 1) / SB;
   auto blk = as_const(p.B);
   for (int q = 0; q < nb; ++q) {
     double acc[SB];
 #pragma unroll
     for (int t = 0; t < SB; ++t) acc[t] = 0.0;
-    for (int pb = 0; pb < q; ++pb, blk += SB * SB) {
-      const double *Yp = Y + static_cast<int64_t>(pb) * SB * ld;
-#pragma unroll 8
-      for (int u = 0; u < SB; ++u) {
-        const double yv = Yp[u * ld];
+    if (q > 0) {
+      f64x4 c[4];
 #pragma unroll
-        for (int t = 0; t < SB; ++t) acc[t] = fma(blk[u * SB + t], yv, acc[t]);
+      for (int mt = 0; mt < 4; ++mt) c[mt] = f64x4{0.0, 0.0, 0.0, 0.0};
+      const auto Bq = as_global(p.B + static_cast<int64_t>(q) * (q + 1) / 2 * SB * SB);
+      const auto Yw = as_global(p.Y + w0 + (lane & 15) + static_cast<int64_t>(lane >> 4) * ld);
+      for (int pb = 0; pb < q; ++pb) {
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const double bv = Bq[pb * SB * SB + ks * 64 + lane];
+          const auto Yr = Yw + static_cast<int64_t>(pb * SB + ks * 4) * ld;
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt) c[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(Yr[mt * 16], bv, c[mt], 0, 0, 0);
+        }
+      }
+      blk += static_cast<int64_t>(q) * SB * SB;
+      // matrix layout -> one lane per sample, 32 samples at a time
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) tr[(mt * 16 + mfma64_row(lane, r)) * kTrLd + (lane & 15)] = c[2 * h + mt][r];
+        __builtin_amdgcn_wave_barrier();
+        if ((lane >> 5) == h) {
+#pragma unroll
+          for (int t = 0; t < SB; ++t) acc[t] = tr[(lane & 31) * kTrLd + t];
+        }
+        __builtin_amdgcn_wave_barrier();
       }
     }
     const int rows = min(SB, p.mj - q * SB);
@@ -166,18 +213,22 @@ __device__ __forceinline__ void sweep_body(const SweepParams &p, int64_t si) {
     }
     blk += SB * SB;
   }
-  p.logp[si] = lp;
+  if (live) p.logp[si] = lp;
 }
 
 template <bool TWO_SIDED, bool SCALED, bool PREC>
 __global__ __launch_bounds__(256) void k_sweep(SweepParams p) {
-  sweep_body<TWO_SIDED, SCALED, PREC>(p, static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x);
+  __shared__ double tr[4 * 32 * kTrLd];
+  sweep_body<TWO_SIDED, SCALED, PREC>(p, static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x,
+                                      tr + (threadIdx.x >> 6) * 32 * kTrLd);
 }
 
 template <bool TWO_SIDED, bool SCALED, bool PREC>
 __global__ __launch_bounds__(256) void k_sweep_batch(const SweepParams *ps) {
+  __shared__ double tr[4 * 32 * kTrLd];
   const SweepParams p = load_uniform(ps + blockIdx.y);
-  sweep_body<TWO_SIDED, SCALED, PREC>(p, static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x);
+  sweep_body<TWO_SIDED, SCALED, PREC>(p, static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x,
+                                      tr + (threadIdx.x >> 6) * 32 * kTrLd);
 }
 
 // ------------------------------------------------------- low rank, FP64 ----

@@ -593,6 +593,8 @@ int tlrqmc_server::step(StepBatch &B, int cur) {
   for (int v = 0; v < 8; ++v) o_sw[v] = stage(B.sweep[v].data(), B.sweep[v].size() * sizeof(SweepParams));
   const size_t o_red = stage(B.reduce.data(), B.reduce.size() * sizeof(ReduceParams));
   if (off > desc_bytes) return 5;  // cannot happen with kMaxSlots slots
+  // kernel launches: no library factorization (setup workers) runs beside them
+  SharedDevice dev;
   hipStream_t st = rctx.stream;
   char *d = d_desc[cur];
   if (hipMemcpyAsync(d, h, off, hipMemcpyHostToDevice, st) != hipSuccess) return 1;

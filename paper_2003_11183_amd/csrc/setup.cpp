@@ -316,11 +316,7 @@ namespace {
 using clk = std::chrono::steady_clock;
 double secs(clk::time_point a, clk::time_point b) { return std::chrono::duration<double>(b - a).count(); }
 
-// rocSOLVER / rocBLAS factorizations from several host threads at once (each
-// with its own handle and stream) gave factors that differed from run to run;
-// one at a time they are reproducible.  Every factorization call of the
-// library holds this lock (tile compression and layouts stay concurrent).
-std::mutex g_blas_mutex;
+thread_local int t_shared_depth = 0;  // shared holds of the device lock by this thread
 
 // The context's rocBLAS handle on its stream (created on first use).
 rocblas_handle blas_of(tlrqmc_ctx *ctx) {
@@ -368,9 +364,13 @@ int build_cov(tlrqmc_ctx *ctx, int64_t n, const tlrqmc_cov *cov, const std::vect
     }
     double *dxy = static_cast<double *>(ctx->dmalloc(2 * n * sizeof(double)));
     if (!dxy) return fail(TLRQMC_ENOMEM, "device allocation failed");
-    hipMemcpyAsync(dxy, xyp.data(), 2 * n * sizeof(double), hipMemcpyHostToDevice, s);
-    launch_cov_exp(s, n, dxy, cov->range, cov->variance, cov->nugget, A, lda, 0, n);
-    const hipError_t e = hipStreamSynchronize(s);
+    hipError_t e;
+    {
+      SharedDevice dev;
+      hipMemcpyAsync(dxy, xyp.data(), 2 * n * sizeof(double), hipMemcpyHostToDevice, s);
+      launch_cov_exp(s, n, dxy, cov->range, cov->variance, cov->nugget, A, lda, 0, n);
+      e = hipStreamSynchronize(s);
+    }
     ctx->dfree(dxy);
     if (e != hipSuccess) return fail(TLRQMC_EDEVICE, "covariance kernel failed");
   } else {
@@ -391,7 +391,8 @@ int device_potrf(tlrqmc_ctx *ctx, rocblas_handle h, int64_t n, double *A, int64_
   std::unique_ptr<rocblas_int, std::function<void(rocblas_int *)>> iguard(dinfo, [ctx](rocblas_int *q) { ctx->dfree(q); });
   rocblas_int info = 0;
   {
-    std::lock_guard<std::mutex> g(g_blas_mutex);
+    ExclusiveDevice dev;
+    if (!dev.ok) return fail(TLRQMC_EDEVICE, "device synchronize failed");
     if (rocsolver_dpotrf(h, rocblas_fill_lower, static_cast<rocblas_int>(n), A, static_cast<rocblas_int>(lda), dinfo) !=
             rocblas_status_success ||
         hipMemcpyAsync(&info, dinfo, sizeof info, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
@@ -533,11 +534,14 @@ int rbodr_eliminate(tlrqmc_ctx *ctx, rocblas_handle h, double *A, int64_t lda, i
     // score the remaining full blocks on the current conditional problem
     const int cnt = j < nsort ? nsort - j : 1;
     const int mb_last = j < nsort ? m : mj;
-    launch_pack_diag(s, A, lda, j0, m, mb_last, cnt, d_pack);
-    if (hipMemcpyAsync(h_pack, d_pack, static_cast<size_t>(cnt) * mm * sizeof(double), hipMemcpyDeviceToHost, s) !=
-            hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return fail(TLRQMC_EDEVICE, "copy of the diagonal blocks failed");
+    {
+      SharedDevice dev;
+      launch_pack_diag(s, A, lda, j0, m, mb_last, cnt, d_pack);
+      if (hipMemcpyAsync(h_pack, d_pack, static_cast<size_t>(cnt) * mm * sizeof(double), hipMemcpyDeviceToHost,
+                         s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return fail(TLRQMC_EDEVICE, "copy of the diagonal blocks failed");
+    }
     std::vector<double> score(cnt);
     std::vector<std::vector<int>> order(cnt);
     std::vector<std::vector<double>> ymean(cnt);
@@ -573,8 +577,11 @@ int rbodr_eliminate(tlrqmc_ctx *ctx, rocblas_handle h, double *A, int64_t lda, i
           hipMemcpyAsync(d_src, src.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
           hipMemcpyAsync(d_slot, slot.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess)
         return fail(TLRQMC_EDEVICE, "copy of the reordering failed");
-      launch_permute_rows(s, A, lda, n, j0, static_cast<int>(rows.size()), d_rows, d_src, d_slot, d_tmp);
-      if (hipStreamSynchronize(s) != hipSuccess) return fail(TLRQMC_EDEVICE, "reordering kernel failed");
+      {
+        SharedDevice dev;
+        launch_permute_rows(s, A, lda, n, j0, static_cast<int>(rows.size()), d_rows, d_src, d_slot, d_tmp);
+        if (hipStreamSynchronize(s) != hipSuccess) return fail(TLRQMC_EDEVICE, "reordering kernel failed");
+      }
       std::vector<int32_t> np(rows.size());
       std::vector<double> na(rows.size()), nb(rows.size());
       for (size_t k = 0; k < rows.size(); ++k) {
@@ -602,7 +609,8 @@ int rbodr_eliminate(tlrqmc_ctx *ctx, rocblas_handle h, double *A, int64_t lda, i
       double *P = Ajj + mj;
       if (hipMemcpyAsync(d_y, ymean[t].data(), mj * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
         return fail(TLRQMC_EDEVICE, "copy failed");
-      std::lock_guard<std::mutex> g(g_blas_mutex);
+      ExclusiveDevice dev;
+      if (!dev.ok) return fail(TLRQMC_EDEVICE, "device synchronize failed");
       if (rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
                         rocblas_diagonal_non_unit, static_cast<rocblas_int>(rest), mj, &one, Ajj,
                         static_cast<rocblas_int>(lda), P, static_cast<rocblas_int>(lda)) != rocblas_status_success ||
@@ -626,7 +634,61 @@ int rbodr_eliminate(tlrqmc_ctx *ctx, rocblas_handle h, double *A, int64_t lda, i
 
 }  // namespace
 
-std::mutex &blas_mutex() { return g_blas_mutex; }
+void DeviceLock::lock_shared() {
+  std::unique_lock<std::mutex> l(mu_);
+  cv_.wait(l, [&] { return !writer_ && writers_waiting_ == 0; });
+  ++readers_;
+}
+
+void DeviceLock::unlock_shared() {
+  std::lock_guard<std::mutex> l(mu_);
+  if (--readers_ == 0) cv_.notify_all();
+}
+
+void DeviceLock::lock() {
+  std::unique_lock<std::mutex> l(mu_);
+  ++writers_waiting_;
+  cv_.wait(l, [&] { return !writer_ && readers_ == 0; });
+  --writers_waiting_;
+  writer_ = true;
+}
+
+void DeviceLock::unlock() {
+  std::lock_guard<std::mutex> l(mu_);
+  writer_ = false;
+  cv_.notify_all();
+}
+
+DeviceLock &device_lock() {
+  static DeviceLock d;
+  return d;
+}
+
+SharedDevice::SharedDevice() {
+  if (t_shared_depth++ == 0) device_lock().lock_shared();
+}
+
+SharedDevice::~SharedDevice() {
+  if (--t_shared_depth == 0) device_lock().unlock_shared();
+}
+
+ExclusiveDevice::ExclusiveDevice() {
+  held_shared_ = t_shared_depth;
+  if (held_shared_ > 0) {
+    t_shared_depth = 0;
+    device_lock().unlock_shared();
+  }
+  device_lock().lock();
+  ok = hipDeviceSynchronize() == hipSuccess;
+}
+
+ExclusiveDevice::~ExclusiveDevice() {
+  device_lock().unlock();
+  if (held_shared_ > 0) {
+    device_lock().lock_shared();
+    t_shared_depth = held_shared_;
+  }
+}
 
 rocblas_handle_t blas_handle(tlrqmc_ctx *ctx) { return blas_of(ctx); }
 
@@ -656,8 +718,11 @@ int factor_from_device_dense(tlrqmc_ctx *ctx, int64_t n, const double *S, int64_
   std::unique_ptr<int32_t, std::function<void(int32_t *)>> pguard(dp, [ctx](int32_t *q) { ctx->dfree(q); });
   if (hipMemcpyAsync(dp, p.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess)
     return fail(TLRQMC_EDEVICE, "copy of the order failed");
-  launch_gather_sym(s, S, lds, dp, A, lda, n);
-  if (hipStreamSynchronize(s) != hipSuccess) return fail(TLRQMC_EDEVICE, "covariance gather failed");
+  {
+    SharedDevice dev;
+    launch_gather_sym(s, S, lds, dp, A, lda, n);
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(TLRQMC_EDEVICE, "covariance gather failed");
+  }
   rocblas_handle h = blas_of(ctx);
   if (!h) return fail(TLRQMC_EDEVICE, "rocblas_create_handle failed");
   int st;

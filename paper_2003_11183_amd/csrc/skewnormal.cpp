@@ -72,8 +72,12 @@ int tlrqmc_skewnormal_loglik(tlrqmc_ctx *ctx, int64_t n, const double *xy, const
   if (hipMemcpyAsync(dxy, xy, 2 * n * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(dr, r.data(), n * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
     return fail(TLRQMC_EDEVICE, "copy of the inputs failed");
-  launch_cov_exp(s, n, dxy, prm->beta1, prm->sigma1 * prm->sigma1, 0.0, K1, lda, 0, n);
-  launch_cov_exp(s, n, dxy, prm->beta2, prm->sigma2 * prm->sigma2, 0.0, B, lda, 0, n);
+  {
+    SharedDevice dev;
+    launch_cov_exp(s, n, dxy, prm->beta1, prm->sigma1 * prm->sigma1, 0.0, K1, lda, 0, n);
+    launch_cov_exp(s, n, dxy, prm->beta2, prm->sigma2 * prm->sigma2, 0.0, B, lda, 0, n);
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(TLRQMC_EDEVICE, "covariance kernels failed");
+  }
   const rocblas_int N = static_cast<rocblas_int>(n), LD = static_cast<rocblas_int>(lda);
   const double one = 1.0, zero = 0.0;
   // Omega = K1 + B B^T and its Cholesky factor: log det and the quadratic form
@@ -81,17 +85,21 @@ int tlrqmc_skewnormal_loglik(tlrqmc_ctx *ctx, int64_t n, const double *xy, const
                        hipMemcpyDeviceToDevice, s) != hipSuccess)
     return fail(TLRQMC_EDEVICE, "copy failed");
   {
-    std::lock_guard<std::mutex> g(blas_mutex());
-    if (rocblas_dsyrk(h, rocblas_fill_lower, rocblas_operation_none, N, N, &one, B, LD, &one, W, LD) !=
-        rocblas_status_success)
+    ExclusiveDevice dev;
+    if (!dev.ok ||
+        rocblas_dsyrk(h, rocblas_fill_lower, rocblas_operation_none, N, N, &one, B, LD, &one, W, LD) !=
+            rocblas_status_success ||
+        hipStreamSynchronize(s) != hipSuccess)
       return fail(TLRQMC_EDEVICE, "rocBLAS syrk failed");
   }
   if ((st = device_cholesky(ctx, W, lda, n))) return st;
   if (hipMemcpyAsync(dt, dr, n * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(TLRQMC_EDEVICE, "copy failed");
   {
-    std::lock_guard<std::mutex> g(blas_mutex());
-    if (rocblas_dtrsv(h, rocblas_fill_lower, rocblas_operation_none, rocblas_diagonal_non_unit, N, W, LD, dt, 1) !=
-        rocblas_status_success)
+    ExclusiveDevice dev;
+    if (!dev.ok ||
+        rocblas_dtrsv(h, rocblas_fill_lower, rocblas_operation_none, rocblas_diagonal_non_unit, N, W, LD, dt, 1) !=
+            rocblas_status_success ||
+        hipStreamSynchronize(s) != hipSuccess)
       return fail(TLRQMC_EDEVICE, "rocBLAS trsv failed");
   }
   if (hipMemcpy2DAsync(dg.data(), sizeof(double), W, (lda + 1) * sizeof(double), sizeof(double), n,
@@ -108,9 +116,14 @@ int tlrqmc_skewnormal_loglik(tlrqmc_ctx *ctx, int64_t n, const double *xy, const
   // A = chol(K1); C = A^-1 B; G = I + C^T C; c = G^-1 C^T A^-1 r; Gamma = G^-1
   if ((st = device_cholesky(ctx, K1, lda, n))) return st;
   if (hipMemcpyAsync(dt, dr, n * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(TLRQMC_EDEVICE, "copy failed");
-  launch_set_identity(s, W, lda, n);
   {
-    std::lock_guard<std::mutex> g(blas_mutex());
+    SharedDevice dev;
+    launch_set_identity(s, W, lda, n);
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(TLRQMC_EDEVICE, "identity kernel failed");
+  }
+  {
+    ExclusiveDevice dev;
+    if (!dev.ok) return fail(TLRQMC_EDEVICE, "device synchronize failed");
     if (rocblas_dtrsm(h, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none, rocblas_diagonal_non_unit, N,
                       N, &one, K1, LD, B, LD) != rocblas_status_success ||
         rocblas_dsyrk(h, rocblas_fill_lower, rocblas_operation_transpose, N, N, &one, B, LD, &one, W, LD) !=
@@ -118,15 +131,16 @@ int tlrqmc_skewnormal_loglik(tlrqmc_ctx *ctx, int64_t n, const double *xy, const
         rocblas_dtrsv(h, rocblas_fill_lower, rocblas_operation_none, rocblas_diagonal_non_unit, N, K1, LD, dt, 1) !=
             rocblas_status_success ||
         rocblas_dgemv(h, rocblas_operation_transpose, N, N, &one, B, LD, dt, 1, &zero, ds, 1) !=
-            rocblas_status_success)
+            rocblas_status_success ||
+        hipStreamSynchronize(s) != hipSuccess)
       return fail(TLRQMC_EDEVICE, "rocBLAS update failed");
   }
   if ((st = device_cholesky(ctx, W, lda, n))) return st;
   {
-    std::lock_guard<std::mutex> g(blas_mutex());
     rocblas_int *dinfo = sc.get<rocblas_int>(1);
     rocblas_int info = 0;
-    if (!dinfo ||
+    ExclusiveDevice dev;
+    if (!dinfo || !dev.ok ||
         rocblas_dtrsv(h, rocblas_fill_lower, rocblas_operation_none, rocblas_diagonal_non_unit, N, W, LD, ds, 1) !=
             rocblas_status_success ||
         rocblas_dtrsv(h, rocblas_fill_lower, rocblas_operation_transpose, rocblas_diagonal_non_unit, N, W, LD, ds,
