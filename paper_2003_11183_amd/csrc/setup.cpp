@@ -390,14 +390,17 @@ int device_potrf(tlrqmc_ctx *ctx, rocblas_handle h, int64_t n, double *A, int64_
   if (!dinfo) return fail(TLRQMC_ENOMEM, "device allocation failed");
   std::unique_ptr<rocblas_int, std::function<void(rocblas_int *)>> iguard(dinfo, [ctx](rocblas_int *q) { ctx->dfree(q); });
   rocblas_int info = 0;
+  rocblas_int *hinfo = reinterpret_cast<rocblas_int *>(ctx->pinned(5, sizeof(rocblas_int)));
+  if (!hinfo) return fail(TLRQMC_ENOMEM, "pinned host allocation failed");
   {
     ExclusiveDevice dev;
     if (!dev.ok) return fail(TLRQMC_EDEVICE, "device synchronize failed");
     if (rocsolver_dpotrf(h, rocblas_fill_lower, static_cast<rocblas_int>(n), A, static_cast<rocblas_int>(lda), dinfo) !=
             rocblas_status_success ||
-        hipMemcpyAsync(&info, dinfo, sizeof info, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipMemcpyAsync(hinfo, dinfo, sizeof info, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
         hipStreamSynchronize(ctx->stream) != hipSuccess)
       return fail(TLRQMC_EDEVICE, "Cholesky failed on the device");
+    info = *hinfo;
   }
   if (info > 0)
     return fail(TLRQMC_ENOTSPD, "covariance not positive definite at column %lld (tile %lld)",

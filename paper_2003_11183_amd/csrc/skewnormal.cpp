@@ -102,11 +102,17 @@ int tlrqmc_skewnormal_loglik(tlrqmc_ctx *ctx, int64_t n, const double *xy, const
         hipStreamSynchronize(s) != hipSuccess)
       return fail(TLRQMC_EDEVICE, "rocBLAS trsv failed");
   }
-  if (hipMemcpy2DAsync(dg.data(), sizeof(double), W, (lda + 1) * sizeof(double), sizeof(double), n,
-                       hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(t.data(), dt, n * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+  // read back through pinned memory: a strided copy into pageable memory was
+  // not always complete when the stream synchronization returned
+  double *hp = ctx->pinned(4, 2 * n * sizeof(double));
+  if (!hp) return fail(TLRQMC_ENOMEM, "pinned host allocation failed");
+  if (hipMemcpy2DAsync(hp, sizeof(double), W, (lda + 1) * sizeof(double), sizeof(double), n, hipMemcpyDeviceToHost,
+                       s) != hipSuccess ||
+      hipMemcpyAsync(hp + n, dt, n * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return fail(TLRQMC_EDEVICE, "copy failed");
+  std::memcpy(dg.data(), hp, n * sizeof(double));
+  std::memcpy(t.data(), hp + n, n * sizeof(double));
   double logdet = 0.0, quad = 0.0;
   for (int64_t i = 0; i < n; ++i) {
     logdet += 2.0 * std::log(dg[i]);
@@ -146,10 +152,11 @@ int tlrqmc_skewnormal_loglik(tlrqmc_ctx *ctx, int64_t n, const double *xy, const
         rocblas_dtrsv(h, rocblas_fill_lower, rocblas_operation_transpose, rocblas_diagonal_non_unit, N, W, LD, ds,
                       1) != rocblas_status_success ||
         rocsolver_dpotri(h, rocblas_fill_lower, N, W, LD, dinfo) != rocblas_status_success ||
-        hipMemcpyAsync(&info, dinfo, sizeof info, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(c.data(), ds, n * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess || info != 0)
+        hipMemcpyAsync(hp + n, dinfo, sizeof info, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(hp, ds, n * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess || (std::memcpy(&info, hp + n, sizeof info), info != 0))
       return fail(TLRQMC_EDEVICE, "inverse of I + C^T C failed");
+    std::memcpy(c.data(), hp, n * sizeof(double));
   }
   if (c_out) std::memcpy(c_out, c.data(), n * sizeof(double));
   t1 = clk::now();
