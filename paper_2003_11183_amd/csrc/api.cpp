@@ -213,7 +213,7 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
   // launches overlap (see tlrqmc_ctx::workers).
   const bool prec = opts->precision == 1;
   const int64_t mpad = round_up(f->m, 64);
-  const int64_t per_sample = prec ? 4 * f->zp_tot + 12 * mpad + 16 : 8 * (f->k_tot + 2 * mpad + 2);
+  const int64_t per_sample = prec ? 4 * f->zp_tot + 8 * mpad + 16 : 8 * (f->k_tot + 2 * mpad + 2);
   const int nstream = count >= kMultiStreamSamples ? kWorkerStreams : 1;
   int64_t chunk = opts->chunk_samples;
   if (chunk <= 0) {
@@ -233,7 +233,8 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
     return fail(TLRQMC_ENOMEM, "device allocation failed");
   struct Lane {
     hipStream_t s;
-    double *Y, *Dl, *Z, *R;
+    void *Y;  // FP32 in the precision form
+    double *Dl, *Z, *R;
     float *DlF, *ZF;
   };
   std::vector<Lane> lanes(nstream);
@@ -241,7 +242,8 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
   for (int w = 0; w < nstream; ++w) {
     Lane &L = lanes[w];
     L.s = nstream > 1 ? ctx->workers[w] : ctx->stream;
-    L.Y = sc.get<double>(static_cast<size_t>(mpad) * ld);
+    L.Y = prec ? static_cast<void *>(sc.get<float>(static_cast<size_t>(mpad) * ld))
+               : static_cast<void *>(sc.get<double>(static_cast<size_t>(mpad) * ld));
     L.Dl = (!prec && r > 1) ? sc.get<double>(static_cast<size_t>(mpad) * ld) : nullptr;
     L.Z = (!prec && f->k_tot > 0) ? sc.get<double>(static_cast<size_t>(f->k_tot) * ld) : nullptr;
     L.DlF = (prec && r > 1) ? sc.get<float>(static_cast<size_t>(mpad) * ld) : nullptr;
@@ -317,11 +319,13 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
           if (prec) {
             const unsigned short *v = f->d_vbf + f->vbf_off[j];
             MfmaLrParams zp{cnt, ld, static_cast<int>(f->kcol[j]), f->tm[j], f->vbf_mp[j], v,
-                            v + f->vbf_size[j], nullptr, L.Y, f->d_zmapp + f->zmap_off[j], L.ZF};
+                            v + f->vbf_size[j], static_cast<const float *>(L.Y), nullptr,
+                            f->d_zmapp + f->zmap_off[j], L.ZF};
             launch_lr_mfma(L.s, zp);
           } else {
             LrParams lp{cnt, ld, static_cast<int>(f->kcol[j]), f->tm[j], f->vpan_ld[j],
-                        f->d_vpan + f->vpan_off[j], L.Y, L.Z, f->d_zmap + f->zmap_off[j]};
+                        f->d_vpan + f->vpan_off[j], static_cast<const double *>(L.Y), L.Z,
+                        f->d_zmap + f->zmap_off[j]};
             launch_zproj_f64(L.s, lp);
           }
           prof.end(L.s);

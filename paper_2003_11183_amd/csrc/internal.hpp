@@ -234,7 +234,7 @@ struct SweepParams {
   const double *R;         // per chunk sample, or null
   const uint64_t *A, *D;
   double *logp;            // per chunk sample
-  double *Y;               // tile rows x ld
+  void *Y;                 // tile rows x ld: FP32 in the precision form, FP64 otherwise
 };
 
 struct LrParams {

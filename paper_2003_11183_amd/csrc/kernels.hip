@@ -70,8 +70,10 @@ __global__ __launch_bounds__(256) void k_init_batch(const InitParams *ps) {
 // overlaps the previous row's special functions.  The load is unconditional:
 // a tile without a low-rank update reads a zero with zero strides.
 //
-// PREC selects the precision form: the low-rank update arrives in FP32 and
-// the one-sided step takes its special functions in FP32.
+// PREC selects the precision form: the low-rank update arrives in FP32, the
+// one-sided step takes its special functions in FP32, and y is stored in FP32
+// (its FP32 quantile is accurate to about 2e-7 already); the products with
+// the diagonal tile stay FP64 arithmetic, on y widened back to FP64.
 //
 // Rows of earlier blocks enter through FP64 matrix cores: for row block q a
 // wave forms C(64 samples x 16 rows) = sum_{p<q} Y_p(64 x 16) B(q,p)^T with
@@ -110,7 +112,7 @@ template <bool TWO_SIDED, bool SCALED, bool PREC>
 __device__ __forceinline__ void sweep_body(const SweepParams &p, int64_t si, double *tr) {
   constexpr int SB = kSweepBlock;
   static_assert(SB == 16, "the matrix-core block products assume 16-row blocks");
-  using DT = typename std::conditional<PREC, float, double>::type;
+  using DT = typename std::conditional<PREC, float, double>::type;  // low-rank update and y
   const int lane = static_cast<int>(threadIdx.x) & 63;
   const int64_t w0 = si - lane;
   if (w0 >= p.count) return;  // whole wave past the end
@@ -125,7 +127,7 @@ __device__ __forceinline__ void sweep_body(const SweepParams &p, int64_t si, dou
   const auto al = as_const(p.a);
   const double R = SCALED ? p.R[sl] : 1.0;
   const int64_t ld = p.ld;
-  double *Y = p.Y + si;
+  DT *Y = static_cast<DT *>(p.Y) + si;
   const bool has_delta = p.Delta != nullptr;
   const DT *Dl = has_delta ? static_cast<const DT *>(p.Delta) + si
                            : (PREC ? reinterpret_cast<const DT *>(&kNoDelta32)
@@ -143,14 +145,15 @@ __device__ __forceinline__ void sweep_body(const SweepParams &p, int64_t si, dou
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt) c[mt] = f64x4{0.0, 0.0, 0.0, 0.0};
       const auto Bq = as_global(p.B + static_cast<int64_t>(q) * (q + 1) / 2 * SB * SB);
-      const auto Yw = as_global(p.Y + w0 + (lane & 15) + static_cast<int64_t>(lane >> 4) * ld);
+      const auto Yw = as_global(static_cast<const DT *>(p.Y) + w0 + (lane & 15) + static_cast<int64_t>(lane >> 4) * ld);
       for (int pb = 0; pb < q; ++pb) {
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
           const double bv = Bq[pb * SB * SB + ks * 64 + lane];
           const auto Yr = Yw + static_cast<int64_t>(pb * SB + ks * 4) * ld;
 #pragma unroll
-          for (int mt = 0; mt < 4; ++mt) c[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(Yr[mt * 16], bv, c[mt], 0, 0, 0);
+          for (int mt = 0; mt < 4; ++mt)
+            c[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(static_cast<double>(Yr[mt * 16]), bv, c[mt], 0, 0, 0);
         }
       }
       blk += static_cast<int64_t>(q) * SB * SB;
@@ -205,7 +208,7 @@ __device__ __forceinline__ void sweep_body(const SweepParams &p, int64_t si, dou
           lp += PREC ? sov_step_upper_fp32((bt - acc[0]) * dinv, w, y)
                      : sov_step_upper((bt - acc[0]) * dinv, w, y);
         }
-        Y[row * ld] = y;
+        Y[row * ld] = static_cast<DT>(y);
 #pragma unroll
         for (int i = 1; i < SB; ++i) acc[i - 1] = fma(c[i - 1], y, acc[i]);
         acc[SB - 1] = 0.0;

@@ -92,9 +92,20 @@ __device__ __forceinline__ void lr_mfma_body(const MfmaLrParams &p, unsigned bid
       v[e] = (sok && k < p.K) ? B[static_cast<int64_t>(k) * p.ld + ss] : TB(0);
     }
   };
-  // One 32-deep step: stage the registers of this step into LDS buffer
-  // buf, refill them with the step two ahead, multiply.
-  auto step = [&](int kk, TB (&v)[8], int buf) {
+  // A operand of one 32-deep step (this wave's row tiles), from global memory.
+  auto load_a = [&](int kk, u16x8 (&ah)[RT], u16x8 (&al)[RT]) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const int64_t ro = static_cast<int64_t>(r0 + 16 * rt + (l & 15)) * p.KP + kk + kq;
+      ah[rt] = *reinterpret_cast<const u16x8 *>(p.Ahi + ro);
+      al[rt] = *reinterpret_cast<const u16x8 *>(p.Alo + ro);
+    }
+  };
+  // One 32-deep step: stage the B registers of this step into LDS buffer
+  // buf, refill them with the step two ahead, fetch the next step's A
+  // operand, multiply with this step's A.
+  auto step = [&](int kk, TB (&v)[8], int buf, u16x8 (&ah)[RT], u16x8 (&al)[RT], u16x8 (&nh)[RT],
+                  u16x8 (&nl)[RT]) {
     u16x8 h, lo;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -107,21 +118,21 @@ __device__ __forceinline__ void lr_mfma_body(const MfmaLrParams &p, unsigned bid
     Bs[buf][1][w][l] = lo;
     __syncthreads();
     if (kk + 64 < p.KP) load_b(kk + 64, v);
+    if (kk + 32 < p.KP) load_a(kk + 32, nh, nl);
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-      const int64_t ro = static_cast<int64_t>(r0 + 16 * rt + (l & 15)) * p.KP + kk + kq;
-      const u16x8 ah = *reinterpret_cast<const u16x8 *>(p.Ahi + ro);
-      const u16x8 al = *reinterpret_cast<const u16x8 *>(p.Alo + ro);
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-      for (int t = 0; t < 4; ++t) acc[rt][t] = mfma3(ah, al, Bs[buf][0][t][l], Bs[buf][1][t][l], acc[rt][t]);
-    }
+      for (int t = 0; t < 4; ++t)
+        acc[rt][t] = mfma3(ah[rt], al[rt], Bs[buf][0][t][l], Bs[buf][1][t][l], acc[rt][t]);
   };
   TB va[8], vb[8];
+  u16x8 a0h[RT], a0l[RT], a1h[RT], a1l[RT];
   load_b(0, va);
   if (32 < p.KP) load_b(32, vb);
+  load_a(0, a0h, a0l);
   for (int kk = 0; kk < p.KP; kk += 64) {
-    step(kk, va, 0);
-    if (kk + 32 < p.KP) step(kk + 32, vb, 1);
+    step(kk, va, 0, a0h, a0l, a1h, a1l);
+    if (kk + 32 < p.KP) step(kk + 32, vb, 1, a1h, a1l, a0h, a0l);
   }
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)

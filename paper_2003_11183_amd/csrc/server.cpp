@@ -159,7 +159,8 @@ struct Slot {
   Request *q = nullptr;
   int64_t c0 = 0, cnt = 0;
   int j = 0;
-  double *Y = nullptr, *Dl = nullptr, *Z = nullptr, *R = nullptr;
+  void *Y = nullptr;  // FP32 in the precision form
+  double *Dl = nullptr, *Z = nullptr, *R = nullptr;
   float *DlF = nullptr, *ZF = nullptr;
 };
 
@@ -368,7 +369,7 @@ bool tlrqmc_server::plan(Request *q) {
   const int r = f->r;
   auto al = [](int64_t b) { return round_up(b, kAlign); };
   auto slot_bytes = [&](int64_t ld) {
-    int64_t b = al(8 * mpad * ld);
+    int64_t b = al((q->prec ? 4 : 8) * mpad * ld);
     if (r > 1) b += al((q->prec ? 4 : 8) * mpad * ld);
     if (f->k_tot > 0) b += al(q->prec ? 4 * f->zp_tot * ld : 8 * f->k_tot * ld);
     if (q->scaled) b += al(8 * ld);
@@ -455,7 +456,7 @@ bool tlrqmc_server::activate_slot(Request *q) {
     got.push_back(p);
     return p;
   };
-  s.Y = static_cast<double *>(take(8 * mpad * ld));
+  s.Y = take((q->prec ? 4 : 8) * mpad * ld);
   if (f->r > 1) {
     if (q->prec) s.DlF = static_cast<float *>(take(4 * mpad * ld));
     else s.Dl = static_cast<double *>(take(8 * mpad * ld));
@@ -549,12 +550,14 @@ int tlrqmc_server::step(StepBatch &B, int cur) {
         const int rows = static_cast<int>(f->kcol[j]);
         const int rt = lr_mfma_rt(rows);
         B.lr[1][rt_index(rt)].push_back(MfmaLrParams{s.cnt, ld, rows, f->tm[j], f->vbf_mp[j], vv, vv + f->vbf_size[j],
-                                                     nullptr, s.Y, f->d_zmapp + f->zmap_off[j], s.ZF});
+                                                     static_cast<const float *>(s.Y), nullptr,
+                                                     f->d_zmapp + f->zmap_off[j], s.ZF});
         const int64_t blocks = (s.cnt + 63) / 64 * ((rows + 64 * rt - 1) / (64 * rt));
         B.lr_max[1][rt_index(rt)] = std::max(B.lr_max[1][rt_index(rt)], blocks);
       } else {
         B.f64[1].push_back(LrParams{s.cnt, ld, static_cast<int>(f->kcol[j]), f->tm[j], f->vpan_ld[j],
-                                    f->d_vpan + f->vpan_off[j], s.Y, s.Z, f->d_zmap + f->zmap_off[j]});
+                                    f->d_vpan + f->vpan_off[j], static_cast<const double *>(s.Y), s.Z,
+                                    f->d_zmap + f->zmap_off[j]});
         B.f64_max[1] = std::max(B.f64_max[1], s.cnt);
         B.f64_rows[1] = std::max(B.f64_rows[1], static_cast<int>(f->kcol[j]));
       }
@@ -624,7 +627,7 @@ int tlrqmc_server::step(StepBatch &B, int cur) {
   for (int t = 0; t < 3; ++t)
     if (!B.lr[1][t].empty()) {
       launch_lr_mfma_batch(st, reinterpret_cast<const MfmaLrParams *>(d + o_lr[1][t]),
-                           static_cast<int>(B.lr[1][t].size()), kRt[t], true, true, B.lr_max[1][t]);
+                           static_cast<int>(B.lr[1][t].size()), kRt[t], false, true, B.lr_max[1][t]);
       ++nl;
     }
   if (!B.f64[1].empty()) {
