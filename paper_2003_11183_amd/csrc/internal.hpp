@@ -192,6 +192,14 @@ class ExclusiveDevice {
   int held_shared_ = 0;
 };
 
+// ---- dense Cholesky on the device (kernels_chol.hip) ----
+// L L^T = A in place (lower, column-major, leading dimension lda); *info
+// must be zero on entry and receives the 1-based row of the first
+// non-positive pivot.  scratch holds kCholScratch doubles.
+constexpr int kCholBlock = 64;
+constexpr int64_t kCholScratch = kCholBlock * kCholBlock + kCholBlock;
+void launch_cholesky(hipStream_t s, double *A, int64_t lda, int64_t n, int32_t *info, double *scratch);
+
 // ---- dense device linear algebra shared by the clients (setup.cpp) ----
 // The context's rocBLAS handle on its stream (rocblas_handle).
 typedef struct _rocblas_handle *rocblas_handle_t;

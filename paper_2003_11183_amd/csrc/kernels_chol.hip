@@ -1,0 +1,154 @@
+// Dense Cholesky factorization A = L L^T (lower, in place, column-major with
+// leading dimension lda) on the device, right-looking with 64-column panels:
+//   k_chol_diag  : the 64 x 64 diagonal block, in LDS (one work-group); it
+//                  also writes a row-major copy of the block and the
+//                  reciprocals of its diagonal to a small scratch buffer;
+//   k_chol_trsm  : the panel below it, L21 = A21 L11^-T, one lane per row
+//                  (the row in registers, L11 through scalar loads);
+//   k_chol_syrk  : the trailing update A22 -= L21 L21^T on the lower 64 x 64
+//                  tiles, with FP64 matrix cores (v_mfma_f64_16x16x4_f64).
+// All arithmetic is FP64; the upper triangle of A is not referenced.  The
+// setup step of the estimator (Section 3.3: the Cholesky factor of the
+// covariance, then tile-wise compression) runs on these kernels.
+#include "device_math.hpp"
+#include "internal.hpp"
+
+namespace tlrqmc {
+
+using namespace dev;
+
+namespace {
+
+constexpr int CB = kCholBlock;
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// Diagonal block at (k0, k0), b = min(64, n - k0) rows.  Right-looking over
+// its columns; thread t works on row t % 64 and on the columns of that row
+// congruent to t / 64 modulo 4.  On a non-positive pivot the global row
+// index + 1 goes to *info and every later block leaves at once.
+__global__ __launch_bounds__(256) void k_chol_diag(double *A, int64_t lda, int64_t n, int64_t k0, int32_t *info,
+                                                   double *scratch) {
+  __shared__ double a[CB][CB + 1];
+  if (*info != 0) return;  // an earlier block failed (the same for the whole group)
+  const int t = static_cast<int>(threadIdx.x);
+  const int i = t & (CB - 1), cg = t >> 6;
+  const int b = static_cast<int>(min<int64_t>(CB, n - k0));
+  double *D = A + k0 * lda + k0;
+  for (int c = cg; c < b; c += 4)
+    if (i < b && i >= c) a[i][c] = D[c * lda + i];
+  __syncthreads();
+  for (int j = 0; j < b; ++j) {
+    const double ajj = a[j][j];
+    if (!(ajj > 0.0)) {  // every thread reads the same value: a uniform exit
+      if (t == 0) *info = static_cast<int32_t>(k0 + j + 1);
+      return;
+    }
+    const double d = sqrt(ajj);
+    __syncthreads();
+    if (cg == 0 && i == j) a[j][j] = d;
+    if (cg == 0 && i > j && i < b) a[i][j] /= d;
+    __syncthreads();
+    if (i > j && i < b) {
+      const double lij = a[i][j];
+      for (int l = j + 1 + ((cg - (j + 1)) & 3); l <= i; l += 4) a[i][l] = fma(-lij, a[l][j], a[i][l]);
+    }
+    __syncthreads();
+  }
+  for (int c = cg; c < b; c += 4)
+    if (i < b && i >= c) D[c * lda + i] = a[i][c];
+  // row-major copy (row j of L11 contiguous) and reciprocal diagonal for
+  // the panel solve
+  if (i < b)
+    for (int c = cg; c < CB; c += 4) scratch[i * CB + c] = (c <= i && c < b) ? a[i][c] : 0.0;
+  if (cg == 0) scratch[CB * CB + i] = i < b ? 1.0 / a[i][i] : 0.0;
+}
+
+// Panel rows r >= k0 + 64: x solves x L11^T = a, left-looking: step j
+// loads a_j, forms x_j = (a_j - sum_{c<j} x_c L11(j, c)) / L11(j, j) and
+// stores it, so a column's address lives only within its step.  The row of
+// x stays in registers; row j of L11 comes from the row-major copy in the
+// scratch buffer by scalar loads.
+__global__ __launch_bounds__(256) void k_chol_trsm(double *A, int64_t lda, int64_t n, int64_t k0,
+                                                   const double *scratch) {
+  const int64_t r = k0 + CB + static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (r >= n) return;
+  const auto Lr = as_const(scratch);  // Lr[j * 64 + c] = L11(j, c)
+  const auto inv = as_const(scratch + CB * CB);
+  const uint32_t ro = static_cast<uint32_t>(r);
+  double x[CB];
+#pragma unroll
+  for (int j = 0; j < CB; ++j) {
+    double *col = A + (k0 + j) * lda;
+    double acc = col[ro];
+#pragma unroll
+    for (int c = 0; c < j; ++c) acc = fma(-x[c], Lr[j * CB + c], acc);
+    x[j] = acc * inv[j];
+    col[ro] = x[j];
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Trailing update of the lower tiles of A22 = A(k0+64:, k0+64:): tile
+// (ti, tj), ti >= tj, of nt x nt; each of the four waves computes one
+// 32 x 32 quarter as 2 x 2 matrix-core tiles of 16 x 16 over the 64
+// columns of the panel.  Operand layouts (as for the sweep's block
+// products): A operand lane l = row l % 16, column 4 k + l / 16; B operand
+// lane l = column l % 16 (a row of the panel), k-row 4 k + l / 16; the
+// result lane l holds rows l / 16 + 4 r, column l % 16.
+__global__ __launch_bounds__(256) void k_chol_syrk(double *A, int64_t lda, int64_t n, int64_t k0) {
+  const int64_t tile = blockIdx.x;
+  int ti = static_cast<int>((sqrt(8.0 * static_cast<double>(tile) + 1.0) - 1.0) * 0.5);
+  while (static_cast<int64_t>(ti) * (ti + 1) / 2 > tile) --ti;
+  while (static_cast<int64_t>(ti + 1) * (ti + 2) / 2 <= tile) ++ti;
+  const int tj = static_cast<int>(tile - static_cast<int64_t>(ti) * (ti + 1) / 2);
+  const int w = static_cast<int>(threadIdx.x) >> 6, l = static_cast<int>(threadIdx.x) & 63;
+  const int64_t base = k0 + CB;
+  const int64_t r0 = base + static_cast<int64_t>(ti) * CB + (w >> 1) * 32;
+  const int64_t c0 = base + static_cast<int64_t>(tj) * CB + (w & 1) * 32;
+  const auto P = as_global(A + k0 * lda);  // P[c * lda + row] = L21(row, c)
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int si = 0; si < 2; ++si)
+#pragma unroll
+    for (int sj = 0; sj < 2; ++sj) acc[si][sj] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int ks = 0; ks < CB / 4; ++ks) {
+    const int64_t col = static_cast<int64_t>(ks * 4 + (l >> 4)) * lda;
+    double va[2], vb[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int64_t ra = r0 + s * 16 + (l & 15), rb = c0 + s * 16 + (l & 15);
+      va[s] = ra < n ? P[col + ra] : 0.0;
+      vb[s] = rb < n ? P[col + rb] : 0.0;
+    }
+#pragma unroll
+    for (int si = 0; si < 2; ++si)
+#pragma unroll
+      for (int sj = 0; sj < 2; ++sj) acc[si][sj] = __builtin_amdgcn_mfma_f64_16x16x4f64(va[si], vb[sj], acc[si][sj], 0, 0, 0);
+  }
+#pragma unroll
+  for (int si = 0; si < 2; ++si)
+#pragma unroll
+    for (int sj = 0; sj < 2; ++sj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = r0 + si * 16 + (l >> 4) + 4 * r, col = c0 + sj * 16 + (l & 15);
+        if (row < n && col < n && row >= col) A[col * lda + row] -= acc[si][sj][r];
+      }
+}
+
+}  // namespace
+
+void launch_cholesky(hipStream_t s, double *A, int64_t lda, int64_t n, int32_t *info, double *scratch) {
+  for (int64_t k0 = 0; k0 < n; k0 += CB) {
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, A, lda, n, k0, info, scratch);
+    const int64_t rest = n - k0 - CB;
+    if (rest <= 0) break;
+    hipLaunchKernelGGL(k_chol_trsm, dim3(static_cast<unsigned>((rest + 255) / 256)), dim3(256), 0, s, A, lda, n, k0,
+                       scratch);
+    const int64_t nt = (rest + CB - 1) / CB;
+    hipLaunchKernelGGL(k_chol_syrk, dim3(static_cast<unsigned>(nt * (nt + 1) / 2)), dim3(256), 0, s, A, lda, n, k0);
+  }
+}
+
+}  // namespace tlrqmc

@@ -384,24 +384,40 @@ int build_cov(tlrqmc_ctx *ctx, int64_t n, const tlrqmc_cov *cov, const std::vect
   return TLRQMC_OK;
 }
 
-// Dense Cholesky (lower) of the n x n matrix A on the device.
-int device_potrf(tlrqmc_ctx *ctx, rocblas_handle h, int64_t n, double *A, int64_t lda, int64_t col0, int m) {
-  rocblas_int *dinfo = static_cast<rocblas_int *>(ctx->dmalloc(sizeof(rocblas_int)));
-  if (!dinfo) return fail(TLRQMC_ENOMEM, "device allocation failed");
-  std::unique_ptr<rocblas_int, std::function<void(rocblas_int *)>> iguard(dinfo, [ctx](rocblas_int *q) { ctx->dfree(q); });
-  rocblas_int info = 0;
-  rocblas_int *hinfo = reinterpret_cast<rocblas_int *>(ctx->pinned(5, sizeof(rocblas_int)));
-  if (!hinfo) return fail(TLRQMC_ENOMEM, "pinned host allocation failed");
-  {
-    ExclusiveDevice dev;
-    if (!dev.ok) return fail(TLRQMC_EDEVICE, "device synchronize failed");
-    if (rocsolver_dpotrf(h, rocblas_fill_lower, static_cast<rocblas_int>(n), A, static_cast<rocblas_int>(lda), dinfo) !=
-            rocblas_status_success ||
-        hipMemcpyAsync(hinfo, dinfo, sizeof info, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
-        hipStreamSynchronize(ctx->stream) != hipSuccess)
-      return fail(TLRQMC_EDEVICE, "Cholesky failed on the device");
-    info = *hinfo;
+// Dense Cholesky (lower) of the n x n matrix A on the device, by this
+// library's kernels (kernels_chol.hip): they run beside the estimator
+// kernels like any other (shared device lock).
+int device_potrf(tlrqmc_ctx *ctx, int64_t n, double *A, int64_t lda, int64_t col0, int m) {
+  int32_t *dinfo = static_cast<int32_t *>(ctx->dmalloc(sizeof(int32_t)));
+  double *scratch = static_cast<double *>(ctx->dmalloc(kCholScratch * sizeof(double)));
+  auto release = [&] {
+    ctx->dfree(dinfo);
+    ctx->dfree(scratch);
+  };
+  if (!dinfo || !scratch) {
+    release();
+    return fail(TLRQMC_ENOMEM, "device allocation failed");
   }
+  int32_t *hinfo = reinterpret_cast<int32_t *>(ctx->pinned(5, sizeof(int32_t)));
+  if (!hinfo) {
+    release();
+    return fail(TLRQMC_ENOMEM, "pinned host allocation failed");
+  }
+  hipStream_t s = ctx->stream;
+  bool ok;
+  {
+    SharedDevice dev;
+    ok = hipMemsetAsync(dinfo, 0, sizeof(int32_t), s) == hipSuccess;
+    if (ok) {
+      launch_cholesky(s, A, lda, n, dinfo, scratch);
+      ok = hipGetLastError() == hipSuccess &&
+           hipMemcpyAsync(hinfo, dinfo, sizeof(int32_t), hipMemcpyDeviceToHost, s) == hipSuccess &&
+           hipStreamSynchronize(s) == hipSuccess;
+    }
+  }
+  const int32_t info = ok ? *hinfo : 0;
+  release();
+  if (!ok) return fail(TLRQMC_EDEVICE, "Cholesky failed on the device");
   if (info > 0)
     return fail(TLRQMC_ENOTSPD, "covariance not positive definite at column %lld (tile %lld)",
                 static_cast<long long>(col0 + info - 1), static_cast<long long>((col0 + info - 1) / m));
@@ -605,7 +621,7 @@ int rbodr_eliminate(tlrqmc_ctx *ctx, rocblas_handle h, double *A, int64_t lda, i
     // factor the block, solve the panel below, condition the later limits
     // on the block's truncated means, update the Schur complement
     double *Ajj = A + j0 * lda + j0;
-    if ((st = device_potrf(ctx, h, mj, Ajj, lda, j0, m))) return st;
+    if ((st = device_potrf(ctx, mj, Ajj, lda, j0, m))) return st;
     const int64_t rest = n - j0 - mj;
     if (rest > 0) {
       const double one = 1.0, zero = 0.0, minus = -1.0;
@@ -696,9 +712,7 @@ ExclusiveDevice::~ExclusiveDevice() {
 rocblas_handle_t blas_handle(tlrqmc_ctx *ctx) { return blas_of(ctx); }
 
 int device_cholesky(tlrqmc_ctx *ctx, double *A, int64_t lda, int64_t n) {
-  rocblas_handle h = blas_of(ctx);
-  if (!h) return fail(TLRQMC_EDEVICE, "rocblas_create_handle failed");
-  return device_potrf(ctx, h, n, A, lda, 0, static_cast<int>(std::max<int64_t>(n, 1)));
+  return device_potrf(ctx, n, A, lda, 0, static_cast<int>(std::max<int64_t>(n, 1)));
 }
 
 int factor_from_device_dense(tlrqmc_ctx *ctx, int64_t n, const double *S, int64_t lds, const double *a,
@@ -737,7 +751,7 @@ int factor_from_device_dense(tlrqmc_ctx *ctx, int64_t n, const double *S, int64_
     }
     if ((st = rbodr_eliminate(ctx, h, A, lda, n, m, p, al, bl))) return st;
   } else {
-    if ((st = device_potrf(ctx, h, n, A, lda, 0, m))) return st;
+    if ((st = device_potrf(ctx, n, A, lda, 0, m))) return st;
   }
   phase[0] = secs(t_begin, clk::now());
   if (perm_out) std::copy(p.begin(), p.end(), perm_out);
@@ -828,7 +842,7 @@ int tlr_factor(tlrqmc_ctx *ctx, int64_t n, const tlrqmc_cov *cov, const int32_t 
   if ((st = build_cov(ctx, n, cov, p, A, lda))) return st;
   rocblas_handle h = blas_of(ctx);
   if (!h) return fail(TLRQMC_EDEVICE, "rocblas_create_handle failed");
-  if ((st = device_potrf(ctx, h, n, A, lda, 0, m))) return st;
+  if ((st = device_potrf(ctx, n, A, lda, 0, m))) return st;
   phase[0] = secs(t_begin, clk::now());
   return compress_build(ctx, A, lda, n, m, p, tol, max_rank, phase, Aguard, out);
 }
