@@ -85,11 +85,16 @@ __device__ __forceinline__ void lr_mfma_body(const MfmaLrParams &p, unsigned bid
   const int kq = 8 * (l >> 4);
   using TB = typename std::conditional<BD, double, float>::type;
   const TB *B = BD ? reinterpret_cast<const TB *>(p.Bd) : reinterpret_cast<const TB *>(p.Bf);
+  // Branch-free: a lane past the samples or a k past K reads element 0
+  // (always valid) and keeps zero, so the loads are never predicated away.
+  const auto Bg = dev::as_global(B);
   auto load_b = [&](int kk, TB (&v)[8]) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int k = kk + kq + e;
-      v[e] = (sok && k < p.K) ? B[static_cast<int64_t>(k) * p.ld + ss] : TB(0);
+      const bool ok = sok && k < p.K;
+      const TB x = Bg[ok ? static_cast<int64_t>(k) * p.ld + ss : 0];
+      v[e] = ok ? x : TB(0);
     }
   };
   // A operand of one 32-deep step (this wave's row tiles), from global memory.
