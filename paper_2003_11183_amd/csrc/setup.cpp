@@ -150,7 +150,11 @@ double univariate_conditioning(int m, std::vector<double> &S, std::vector<double
 // Truncated SVD of the mi x mj column-major tile T (leading dimension ldt):
 // keeps the singular values > tol (at most cap when cap > 0).  Writes U
 // (mi x k, row-major, columns scaled by the singular values) and V
-// (mj x k, row-major); returns k and sets capped.
+// (mj x k, row-major); returns k and sets capped.  Column-pivoted
+// Householder QR T P = Q R stops once the trailing columns' norm drops
+// below tol / 1000; the singular values and right vectors of R then come
+// from the eigen-decomposition of the small Gram matrix R R^T (cyclic
+// Jacobi), so the work past the QR grows with the rank, not the tile.
 int compress_tile(const double *T, int64_t ldt, int mi, int mj, double tol, int cap, std::vector<double> &U,
                   std::vector<double> &V, bool &capped) {
   capped = false;
@@ -165,20 +169,36 @@ int compress_tile(const double *T, int64_t ldt, int mi, int mj, double tol, int 
   std::vector<double> tau;
   const double stop = 1e-3 * tol;
   int kq = 0;
+  // squared norms of the trailing columns, updated after each reflection
+  // and recomputed where the update has cancelled most of the value
+  std::vector<double> cn0(mj);
+  for (int c = 0; c < mj; ++c) {
+    double s = 0.0;
+    for (int rr = 0; rr < mi; ++rr) s += Aat(rr, c) * Aat(rr, c);
+    cn[c] = cn0[c] = s;
+  }
   for (; kq < kmax; ++kq) {
     double rest = 0.0;
     int best = kq;
     for (int c = kq; c < mj; ++c) {
-      double s = 0.0;
-      for (int rr = kq; rr < mi; ++rr) s += Aat(rr, c) * Aat(rr, c);
-      cn[c] = s;
-      rest += s;
-      if (s > cn[best]) best = c;
+      if (kq > 0) {
+        const double r = Aat(kq - 1, c);
+        cn[c] -= r * r;
+        if (!(cn[c] > 1e-8 * cn0[c])) {
+          double s = 0.0;
+          for (int rr = kq; rr < mi; ++rr) s += Aat(rr, c) * Aat(rr, c);
+          cn[c] = cn0[c] = s;
+        }
+      }
+      rest += cn[c];
+      if (cn[c] > cn[best]) best = c;
     }
     if (std::sqrt(rest) <= stop) break;
     if (best != kq) {
       for (int rr = 0; rr < mi; ++rr) std::swap(Aat(rr, kq), Aat(rr, best));
       std::swap(piv[kq], piv[best]);
+      std::swap(cn[kq], cn[best]);
+      std::swap(cn0[kq], cn0[best]);
     }
     // Householder reflector for column kq, rows kq..mi-1
     double nrm = 0.0;
@@ -209,36 +229,47 @@ int compress_tile(const double *T, int64_t ldt, int mi, int mj, double tol, int 
   }
   const int kq_final = kq;
   int k = 0;
-  std::vector<double> sig;
-  std::vector<double> Ur, Vr;
   if (kq_final > 0) {
-    // G = R^T (mj x kq) in pivoted column order; one-sided Jacobi on its columns.
-    std::vector<double> G(static_cast<size_t>(mj) * kq_final, 0.0), J(static_cast<size_t>(kq_final) * kq_final, 0.0);
+    // G = R^T (mj x kq) with its rows in the original column order, and the
+    // kq x kq Gram matrix M = G^T G = R R^T, diagonalized by cyclic Jacobi
+    // rotations: M = J diag(lambda) J^T, sigma = sqrt(lambda).
+    std::vector<double> G(static_cast<size_t>(mj) * kq_final, 0.0), J(static_cast<size_t>(kq_final) * kq_final, 0.0),
+        M(static_cast<size_t>(kq_final) * kq_final, 0.0);
     auto Gat = [&](int rr, int c) -> double & { return G[static_cast<size_t>(c) * mj + rr]; };
     auto Jat = [&](int rr, int c) -> double & { return J[static_cast<size_t>(c) * kq_final + rr]; };
+    auto Mat = [&](int rr, int c) -> double & { return M[static_cast<size_t>(c) * kq_final + rr]; };
     for (int c = 0; c < kq_final; ++c) {
       Jat(c, c) = 1.0;
       for (int col = c; col < mj; ++col) Gat(piv[col], c) = Aat(c, col);
     }
+    for (int p = 0; p < kq_final; ++p)
+      for (int q = p; q < kq_final; ++q) {
+        double d = 0.0;
+        for (int col = std::max(p, q); col < mj; ++col) d += Aat(p, col) * Aat(q, col);
+        Mat(p, q) = d;
+        Mat(q, p) = d;
+      }
+    double scale = 0.0;
+    for (int c = 0; c < kq_final; ++c) scale = std::max(scale, std::fabs(Mat(c, c)));
     for (int sweep = 0; sweep < 60; ++sweep) {
       double off = 0.0;
       for (int p = 0; p < kq_final - 1; ++p)
         for (int q = p + 1; q < kq_final; ++q) {
-          double alpha = 0.0, beta = 0.0, gamma = 0.0;
-          for (int rr = 0; rr < mj; ++rr) {
-            alpha += Gat(rr, p) * Gat(rr, p);
-            beta += Gat(rr, q) * Gat(rr, q);
-            gamma += Gat(rr, p) * Gat(rr, q);
+          const double apq = Mat(p, q);
+          if (std::fabs(apq) <= 1e-18 * scale) continue;
+          off = std::max(off, std::fabs(apq) / scale);
+          const double theta = (Mat(q, q) - Mat(p, p)) / (2.0 * apq);
+          const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(1.0 + theta * theta));
+          const double cs = 1.0 / std::sqrt(1.0 + t * t), sn = t * cs;
+          for (int rr = 0; rr < kq_final; ++rr) {  // columns p, q
+            const double mp = Mat(rr, p), mq = Mat(rr, q);
+            Mat(rr, p) = cs * mp - sn * mq;
+            Mat(rr, q) = sn * mp + cs * mq;
           }
-          if (gamma == 0.0 || std::fabs(gamma) <= 1e-17 * std::sqrt(alpha * beta)) continue;
-          off = std::max(off, std::fabs(gamma) / std::sqrt(alpha * beta));
-          const double zeta = (beta - alpha) / (2.0 * gamma);
-          const double tt = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
-          const double cs = 1.0 / std::sqrt(1.0 + tt * tt), sn = cs * tt;
-          for (int rr = 0; rr < mj; ++rr) {
-            const double gp = Gat(rr, p), gq = Gat(rr, q);
-            Gat(rr, p) = cs * gp - sn * gq;
-            Gat(rr, q) = sn * gp + cs * gq;
+          for (int cc = 0; cc < kq_final; ++cc) {  // rows p, q
+            const double mp = Mat(p, cc), mq = Mat(q, cc);
+            Mat(p, cc) = cs * mp - sn * mq;
+            Mat(q, cc) = sn * mp + cs * mq;
           }
           for (int rr = 0; rr < kq_final; ++rr) {
             const double jp = Jat(rr, p), jq = Jat(rr, q);
@@ -246,14 +277,12 @@ int compress_tile(const double *T, int64_t ldt, int mi, int mj, double tol, int 
             Jat(rr, q) = sn * jp + cs * jq;
           }
         }
-      if (off < 1e-15) break;
+      if (off < 1e-17) break;
     }
+    // sigma_c = sqrt(lambda_c); the right vectors G J_c / sigma_c are formed
+    // below for the kept columns only
     std::vector<std::pair<double, int>> sv(kq_final);
-    for (int c = 0; c < kq_final; ++c) {
-      double s = 0.0;
-      for (int rr = 0; rr < mj; ++rr) s += Gat(rr, c) * Gat(rr, c);
-      sv[c] = {std::sqrt(s), c};
-    }
+    for (int c = 0; c < kq_final; ++c) sv[c] = {std::sqrt(std::max(Mat(c, c), 0.0)), c};
     std::sort(sv.begin(), sv.end(), [](const auto &x, const auto &y) {
       return x.first > y.first || (x.first == y.first && x.second < y.second);
     });
@@ -263,7 +292,7 @@ int compress_tile(const double *T, int64_t ldt, int mi, int mj, double tol, int 
       capped = true;
     }
     // Q (mi x kq) from the reflectors, applied to the chosen columns of J:
-    // U = Q J(:, idx) (times sigma), V = G(:, idx) / sigma.
+    // U = Q J(:, idx) (times sigma), V = G J(:, idx) / sigma.
     U.assign(static_cast<size_t>(mi) * k, 0.0);
     V.assign(static_cast<size_t>(mj) * k, 0.0);
     std::vector<double> w(mi);
@@ -281,7 +310,11 @@ int compress_tile(const double *T, int64_t ldt, int mi, int mj, double tol, int 
         for (int rr = h + 1; rr < mi; ++rr) w[rr] -= d * Aat(rr, h);
       }
       for (int rr = 0; rr < mi; ++rr) U[static_cast<size_t>(rr) * k + c] = w[rr];
-      for (int rr = 0; rr < mj; ++rr) V[static_cast<size_t>(rr) * k + c] = Gat(rr, src) / s;
+      for (int rr = 0; rr < mj; ++rr) {
+        double g = 0.0;
+        for (int r2 = 0; r2 < kq_final; ++r2) g += Gat(rr, r2) * Jat(r2, src);
+        V[static_cast<size_t>(rr) * k + c] = g / s;
+      }
     }
   } else {
     U.clear();
