@@ -203,7 +203,8 @@ def main():
                                f"{'FP64' if precision == 0 else 'BF16x3-MFMA low-rank / FP64 sweep'}",
                    "n": n, "m": m, "samples": N, "shifts": M, "precision": precision,
                    "k_tot": st["k_tot"], "k_max": st["k_max"], "cap_hits": st["cap_hits"],
-                   "factor_mb": st["device_bytes"] / 2 ** 20, "setup_s": setup_s},
+                   "factor_mb": st["device_bytes"] / 2 ** 20, "setup_s": setup_s,
+                   "setup_phases_s": st["setup_seconds"], "host_tiles": st["host_tiles"]},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
         "estimate": {"log_p": r0["log_p"], "std_err": r0["std_err"], "rel_err": r0["rel_err"]},
         "value_device_only": N * M * n / dev_s,

@@ -163,10 +163,15 @@ typedef struct {
   int64_t uv_doubles;   /* entries of each exchange U and V array    */
   int64_t device_bytes; /* device memory held by the factor          */
   /* tlr_factor only (0 otherwise), seconds: covariance and Cholesky on
-   * the device, transfer of the factor to the host, compression of the
-   * off-diagonal tiles, device layouts and upload. */
+   * the device, transfer to the host (the diagonal tiles when the device
+   * compresses, else the whole factor), compression of the off-diagonal
+   * tiles, device layouts and upload. */
   double setup_seconds[4];
   uint64_t checksum;    /* FNV-1a hash of the exchange arrays (bit-level identity) */
+  /* tlr_factor only: off-diagonal tiles compressed on the host.  Tiles up to
+   * 512 wide are compressed on the device, except those whose pivoted QR
+   * needs more than 96 steps; wider tiles are all compressed on the host. */
+  int64_t host_tiles;
 } tlrqmc_factor_info;
 
 int tlrqmc_factor_stats(const tlrqmc_factor *f, tlrqmc_factor_info *out);

@@ -472,6 +472,7 @@ int tlrqmc_factor_stats(const tlrqmc_factor *f, tlrqmc_factor_info *o) {
   o->device_bytes = f->device_bytes;
   for (int k = 0; k < 4; ++k) o->setup_seconds[k] = f->setup_seconds[k];
   o->checksum = f->checksum;
+  o->host_tiles = f->host_tiles;
   return TLRQMC_OK;
 }
 

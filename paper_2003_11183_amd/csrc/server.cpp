@@ -246,8 +246,11 @@ namespace tlrqmc {
 namespace {
 
 // Device bytes of setup: the dense covariance (leading dimension padded to
-// 64) and the locations, plus slack for the factor's small arrays.
-int64_t setup_reserve(int64_t n) { return 8 * round_up(n, 64) * n + 64 * n + (int64_t{1} << 20); }
+// 64), the locations and the tile compression's batch buffers, plus slack
+// for the factor's small arrays.
+int64_t setup_reserve(int64_t n, int m) {
+  return 8 * round_up(n, 64) * n + 64 * n + compress_scratch_bytes(n, m) + (int64_t{1} << 20);
+}
 
 }  // namespace
 }  // namespace tlrqmc
@@ -289,19 +292,19 @@ void tlrqmc_server::setup_loop(int w) {
   for (;;) {
     cv.wait(lk, [&] {
       if (queued.empty()) return stop;
-      const int64_t need = setup_reserve(queued.front()->n);
+      const int64_t need = setup_reserve(queued.front()->n, queued.front()->m);
       return need > static_cast<int64_t>(budget) || reserved + need <= static_cast<int64_t>(budget);
     });
     if (queued.empty()) return;
     Request *q = queued.front();
     queued.pop_front();
-    if (setup_reserve(q->n) > static_cast<int64_t>(budget)) {
+    if (setup_reserve(q->n, q->m) > static_cast<int64_t>(budget)) {
       fail_request(q, TLRQMC_ENOMEM,
-                   "setup of the request needs " + std::to_string(setup_reserve(q->n)) +
+                   "setup of the request needs " + std::to_string(setup_reserve(q->n, q->m)) +
                        " bytes of device memory, more than the server budget");
       continue;
     }
-    q->reserve = setup_reserve(q->n);
+    q->reserve = setup_reserve(q->n, q->m);
     reserved += q->reserve;
     peak_reserved = std::max(peak_reserved, reserved);
     q->state = SETUP;

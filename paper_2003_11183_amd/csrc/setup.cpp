@@ -249,15 +249,17 @@ int compress_tile(const double *T, int64_t ldt, int mi, int mj, double tol, int 
         Mat(p, q) = d;
         Mat(q, p) = d;
       }
-    double scale = 0.0;
-    for (int c = 0; c < kq_final; ++c) scale = std::max(scale, std::fabs(Mat(c, c)));
+    // A pair is rotated unless |M_pq| is negligible against sqrt(M_pp M_qq):
+    // R is graded by the pivoting, and this relative test keeps the small
+    // singular values accurate too.
     for (int sweep = 0; sweep < 60; ++sweep) {
       double off = 0.0;
       for (int p = 0; p < kq_final - 1; ++p)
         for (int q = p + 1; q < kq_final; ++q) {
           const double apq = Mat(p, q);
-          if (std::fabs(apq) <= 1e-18 * scale) continue;
-          off = std::max(off, std::fabs(apq) / scale);
+          const double rel = std::sqrt(Mat(p, p) * Mat(q, q));
+          if (!(std::fabs(apq) > 1e-17 * rel)) continue;
+          off = std::max(off, std::fabs(apq) / rel);
           const double theta = (Mat(q, q) - Mat(p, p)) / (2.0 * apq);
           const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(1.0 + theta * theta));
           const double cs = 1.0 / std::sqrt(1.0 + t * t), sn = t * cs;
@@ -459,11 +461,154 @@ int device_potrf(tlrqmc_ctx *ctx, int64_t n, double *A, int64_t lda, int64_t col
 
 // From the dense factor L (lower part of A, order p) to the TLR factor:
 // download by panels, compress the off-diagonal tiles, build the layouts.
+// Device compression (kernels_compress.hip) in batches of tiles: the factor
+// stays on the device; only the diagonal tiles and the packed U and V blocks
+// come back.  A tile whose QR needs more than kCmpKq steps is downloaded and
+// compressed on the host.
+int compress_build_device(tlrqmc_ctx *ctx, double *A, int64_t lda, int64_t n, int m, const std::vector<int32_t> &p,
+                          double tol, int max_rank, double *phase,
+                          std::unique_ptr<double, std::function<void(double *)>> &Aguard, tlrqmc_factor **out) {
+  hipStream_t s = ctx->stream;
+  const int r = static_cast<int>((n + m - 1) / m);
+  std::vector<int> tm(r);
+  for (int i = 0; i < r; ++i) tm[i] = static_cast<int>(std::min<int64_t>(m, n - static_cast<int64_t>(i) * m));
+  std::vector<int64_t> doff(r + 1, 0);
+  for (int i = 0; i < r; ++i) doff[i + 1] = doff[i] + static_cast<int64_t>(tm[i]) * tm[i];
+  const int64_t ntiles = static_cast<int64_t>(r) * (r - 1) / 2;
+  const int64_t B = std::max<int64_t>(1, compress_batch_tiles(n, m));
+  const int64_t wslot = static_cast<int64_t>(m) * m, vslot = compress_vslot(m);
+  Scratch sc(ctx);
+  double *dW = sc.get<double>(B * wslot);
+  double *dV = sc.get<double>(B * vslot);
+  double *dOut = sc.get<double>(B * 2 * vslot);
+  int32_t *dInfo = sc.get<int32_t>(B * 4);
+  int32_t *hInfo = reinterpret_cast<int32_t *>(ctx->pinned(7, B * 4 * sizeof(int32_t)));
+  double *hDiag = ctx->pinned(8, doff[r] * sizeof(double));
+  if (!dW || !dV || !dOut || !dInfo) return fail(TLRQMC_ENOMEM, "device allocation for the compression failed");
+  if (!hInfo || !hDiag) return fail(TLRQMC_ENOMEM, "pinned host staging allocation failed");
+  const auto t_dl = clk::now();
+  {
+    SharedDevice dev;
+    bool ok = true;
+    for (int i = 0; i < r && ok; ++i) {
+      const int64_t c0 = static_cast<int64_t>(i) * m;
+      ok = hipMemcpy2DAsync(hDiag + doff[i], tm[i] * sizeof(double), A + c0 * lda + c0, lda * sizeof(double),
+                            tm[i] * sizeof(double), tm[i], hipMemcpyDeviceToHost, s) == hipSuccess;
+    }
+    if (!ok || hipStreamSynchronize(s) != hipSuccess) return fail(TLRQMC_EDEVICE, "copy of the diagonal tiles failed");
+  }
+  std::vector<double> hdiag(doff[r]);
+  for (int i = 0; i < r; ++i)
+    for (int t = 0; t < tm[i]; ++t)
+      for (int u = 0; u < tm[i]; ++u)
+        hdiag[doff[i] + static_cast<int64_t>(t) * tm[i] + u] =
+            u <= t ? hDiag[doff[i] + static_cast<int64_t>(u) * tm[i] + t] : 0.0;
+  const auto t_cp = clk::now();
+  phase[1] += secs(t_dl, t_cp);
+  std::vector<int32_t> ranks(static_cast<size_t>(r) * r, 0);
+  std::vector<std::vector<double>> Us(static_cast<size_t>(ntiles)), Vs(static_cast<size_t>(ntiles));
+  std::vector<int64_t> left;  // tiles for the host
+  int cap_hits = 0;
+  for (int64_t t0 = 0; t0 < ntiles; t0 += B) {
+    const int count = static_cast<int>(std::min<int64_t>(B, ntiles - t0));
+    {
+      SharedDevice dev;
+      launch_compress(s, A, lda, n, m, t0, count, tol, max_rank, dW, dV, dOut, dInfo);
+      if (hipGetLastError() != hipSuccess ||
+          hipMemcpyAsync(hInfo, dInfo, count * 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return fail(TLRQMC_EDEVICE, "tile compression failed on the device");
+    }
+    int64_t ut = 0, vt = 0;
+    for (int q = 0; q < count; ++q) {
+      int64_t r0, c0;
+      int mi, mj;
+      compress_tile_at(t0 + q, n, m, r0, c0, mi, mj);
+      const int k = (hInfo[4 * q + 2] & 1) ? 0 : hInfo[4 * q + 1];
+      ut += static_cast<int64_t>(mi) * k;
+      vt += static_cast<int64_t>(mj) * k;
+    }
+    double *hOut = ctx->pinned(6, std::max<int64_t>(1, ut + vt) * sizeof(double));
+    if (!hOut) return fail(TLRQMC_ENOMEM, "pinned host staging allocation failed");
+    if (ut + vt > 0) {
+      SharedDevice dev;
+      if (hipMemcpyAsync(hOut, dOut, (ut + vt) * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return fail(TLRQMC_EDEVICE, "copy of the compressed tiles failed");
+    }
+    int64_t uo = 0, vo = ut;
+    for (int q = 0; q < count; ++q) {
+      const int64_t t = t0 + q;
+      int64_t r0, c0;
+      int mi, mj;
+      compress_tile_at(t, n, m, r0, c0, mi, mj);
+      const int i = static_cast<int>(r0 / m), j = static_cast<int>(c0 / m);
+      if (hInfo[4 * q + 2] & 1) {
+        left.push_back(t);
+        continue;
+      }
+      const int k = hInfo[4 * q + 1];
+      ranks[static_cast<size_t>(i) * r + j] = k;
+      cap_hits += (hInfo[4 * q + 2] & 2) ? 1 : 0;
+      Us[t].assign(hOut + uo, hOut + uo + static_cast<int64_t>(mi) * k);
+      Vs[t].assign(hOut + vo, hOut + vo + static_cast<int64_t>(mj) * k);
+      uo += static_cast<int64_t>(mi) * k;
+      vo += static_cast<int64_t>(mj) * k;
+    }
+  }
+  if (!left.empty()) {
+    // tiles beyond the device kernels' QR depth: download and compress here
+    const size_t per = static_cast<size_t>(m) * m;
+    double *hT = ctx->pinned(9, left.size() * per * sizeof(double));
+    if (!hT) return fail(TLRQMC_ENOMEM, "pinned host staging allocation failed");
+    {
+      SharedDevice dev;
+      bool ok = true;
+      for (size_t q = 0; q < left.size() && ok; ++q) {
+        int64_t r0, c0;
+        int mi, mj;
+        compress_tile_at(left[q], n, m, r0, c0, mi, mj);
+        ok = hipMemcpy2DAsync(hT + q * per, mi * sizeof(double), A + c0 * lda + r0, lda * sizeof(double),
+                              mi * sizeof(double), mj, hipMemcpyDeviceToHost, s) == hipSuccess;
+      }
+      if (!ok || hipStreamSynchronize(s) != hipSuccess) return fail(TLRQMC_EDEVICE, "copy of the factor failed");
+    }
+    int hits = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : hits)
+    for (size_t q = 0; q < left.size(); ++q) {
+      int64_t r0, c0;
+      int mi, mj;
+      compress_tile_at(left[q], n, m, r0, c0, mi, mj);
+      bool capped = false;
+      const int k = compress_tile(hT + q * per, mi, mi, mj, tol, max_rank, Us[left[q]], Vs[left[q]], capped);
+      ranks[static_cast<size_t>(r0 / m) * r + c0 / m] = k;
+      hits += capped ? 1 : 0;
+    }
+    cap_hits += hits;
+  }
+  phase[2] += secs(t_cp, clk::now());
+  Aguard.reset();
+  const auto t_layout = clk::now();
+  std::vector<double> hU, hV;
+  for (int64_t t = 0; t < ntiles; ++t) {
+    hU.insert(hU.end(), Us[t].begin(), Us[t].end());
+    hV.insert(hV.end(), Vs[t].begin(), Vs[t].end());
+  }
+  int st = factor_build(ctx, n, m, p.data(), hdiag.data(), ranks.data(), hU.data(), hV.data(), cap_hits, out);
+  if (st) return st;
+  phase[3] = secs(t_layout, clk::now());
+  for (int k = 0; k < 4; ++k) (*out)->setup_seconds[k] = phase[k];
+  (*out)->host_tiles = static_cast<int64_t>(left.size());
+  return cap_hits > 0 ? TLRQMC_WARN_RANKCAP : TLRQMC_OK;
+}
+
 int compress_build(tlrqmc_ctx *ctx, double *A, int64_t lda, int64_t n, int m, const std::vector<int32_t> &p,
                    double tol, int max_rank, double *phase, std::unique_ptr<double, std::function<void(double *)>> &Aguard,
                    tlrqmc_factor **out) {
   hipStream_t s = ctx->stream;
   int st;
+  if (m <= kCmpMaxTile && n > m)
+    return compress_build_device(ctx, A, lda, n, m, p, tol, max_rank, phase, Aguard, out);
   // Column panels of L go to the host in groups, through two pinned staging
   // buffers: the copy of the next group overlaps the compression of this
   // one.  Every off-diagonal tile of a group is compressed in one parallel
@@ -548,6 +693,7 @@ int compress_build(tlrqmc_ctx *ctx, double *A, int64_t lda, int64_t n, int m, co
   if (st) return st;
   phase[3] = secs(t_layout, clk::now());
   for (int k = 0; k < 4; ++k) (*out)->setup_seconds[k] = phase[k];
+  (*out)->host_tiles = static_cast<int64_t>(r) * (r - 1) / 2;
   return cap_hits > 0 ? TLRQMC_WARN_RANKCAP : TLRQMC_OK;
 }
 

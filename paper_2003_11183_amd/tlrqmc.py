@@ -45,7 +45,7 @@ class FactorInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("m", C.c_int32), ("r", C.c_int32), ("k_tot", C.c_int64),
                 ("k_max", C.c_int32), ("cap_hits", C.c_int32), ("diag_doubles", C.c_int64),
                 ("uv_doubles", C.c_int64), ("device_bytes", C.c_int64), ("setup_seconds", C.c_double * 4),
-                ("checksum", C.c_uint64)]
+                ("checksum", C.c_uint64), ("host_tiles", C.c_int64)]
 
 
 class QmcOpts(C.Structure):
