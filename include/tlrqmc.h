@@ -167,7 +167,8 @@ typedef struct {
    * compresses, else the whole factor), compression of the off-diagonal
    * tiles, device layouts and upload. */
   double setup_seconds[4];
-  uint64_t checksum;    /* FNV-1a hash of the exchange arrays (bit-level identity) */
+  uint64_t checksum;    /* hash of the exchange arrays (bit-level identity): FNV-1a
+                         * over 64-bit words of 1 MiB chunks, chunk hashes folded in order */
   /* tlr_factor only: off-diagonal tiles compressed on the host.  Tiles up to
    * 512 wide are compressed on the device, except those whose pivoted QR
    * needs more than 96 steps; wider tiles are all compressed on the host. */

@@ -288,16 +288,33 @@ int factor_build(tlrqmc_ctx *ctx, int64_t n, int m, const int32_t *perm, const d
   if (hipStreamSynchronize(ctx->stream) != hipSuccess) return fail(TLRQMC_EDEVICE, "stream synchronize failed");
   f->device_bytes = total;
   {
+    // FNV-1a over 64-bit words (the last one zero-padded) within 1 MiB
+    // chunks, hashed in parallel; the chunk hashes are folded in order.
+    constexpr size_t kChunk = size_t{1} << 20;
+    const std::pair<const void *, size_t> parts[5] = {{f->perm.data(), f->perm.size() * 4},
+                                                      {f->h_diag.data(), f->h_diag.size() * 8},
+                                                      {f->rank.data(), f->rank.size() * 4},
+                                                      {f->h_U.data(), f->h_U.size() * 8},
+                                                      {f->h_V.data(), f->h_V.size() * 8}};
+    std::vector<std::pair<const unsigned char *, size_t>> chunks;
+    for (const auto &pt : parts)
+      for (size_t o = 0; o < pt.second; o += kChunk)
+        chunks.push_back({static_cast<const unsigned char *>(pt.first) + o, std::min(kChunk, pt.second - o)});
+    std::vector<uint64_t> ch(chunks.size());
+#pragma omp parallel for schedule(dynamic, 4)
+    for (size_t q = 0; q < chunks.size(); ++q) {
+      uint64_t h = 1469598103934665603ull;
+      const unsigned char *c = chunks[q].first;
+      const size_t bytes = chunks[q].second;
+      for (size_t o = 0; o < bytes; o += 8) {
+        uint64_t w = 0;
+        std::memcpy(&w, c + o, std::min<size_t>(8, bytes - o));
+        h = (h ^ w) * 1099511628211ull;
+      }
+      ch[q] = h;
+    }
     uint64_t hsh = 1469598103934665603ull;
-    auto mix = [&hsh](const void *p, size_t bytes) {
-      const unsigned char *c = static_cast<const unsigned char *>(p);
-      for (size_t i = 0; i < bytes; ++i) hsh = (hsh ^ c[i]) * 1099511628211ull;
-    };
-    mix(f->perm.data(), f->perm.size() * 4);
-    mix(f->h_diag.data(), f->h_diag.size() * 8);
-    mix(f->rank.data(), f->rank.size() * 4);
-    mix(f->h_U.data(), f->h_U.size() * 8);
-    mix(f->h_V.data(), f->h_V.size() * 8);
+    for (uint64_t h : ch) hsh = (hsh ^ h) * 1099511628211ull;
     f->checksum = hsh;
   }
   *out = guard.release();

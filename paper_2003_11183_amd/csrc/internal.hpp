@@ -199,6 +199,7 @@ class ExclusiveDevice {
 // must be zero on entry and receives the 1-based row of the first
 // non-positive pivot.  scratch holds kCholScratch doubles.
 constexpr int kCholBlock = 64;
+constexpr int kCholPanel = 256;  // columns per trailing update (a multiple of kCholBlock)
 constexpr int64_t kCholScratch = kCholBlock * kCholBlock + kCholBlock;
 void launch_cholesky(hipStream_t s, double *A, int64_t lda, int64_t n, int32_t *info, double *scratch);
 

@@ -1,15 +1,20 @@
 // Dense Cholesky factorization A = L L^T (lower, in place, column-major with
-// leading dimension lda) on the device, right-looking with 64-column panels:
+// leading dimension lda) on the device, blocked on two levels: panels of 256
+// columns, each factored as four 64-column steps
 //   k_chol_diag  : the 64 x 64 diagonal block, in LDS (one work-group); it
 //                  also writes a row-major copy of the block and the
 //                  reciprocals of its diagonal to a small scratch buffer;
-//   k_chol_trsm  : the panel below it, L21 = A21 L11^-T, one lane per row
-//                  (the row in registers, L11 through scalar loads);
-//   k_chol_syrk  : the trailing update A22 -= L21 L21^T on the lower 64 x 64
-//                  tiles, with FP64 matrix cores (v_mfma_f64_16x16x4_f64).
-// All arithmetic is FP64; the upper triangle of A is not referenced.  The
-// setup step of the estimator (Section 3.3: the Cholesky factor of the
-// covariance, then tile-wise compression) runs on these kernels.
+//   k_chol_trsm  : the column block below it, L21 = A21 L11^-T, one lane per
+//                  row (the row in registers, L11 through scalar loads);
+//   k_chol_syrk  : the update of the rest of the panel's columns by that
+//                  block, on 64 x 64 tiles with FP64 matrix cores
+//                  (v_mfma_f64_16x16x4_f64);
+// then one update of the trailing matrix by the whole panel (k_chol_wide:
+// 128 x 128 tiles, 256-deep products on the matrix cores), so the trailing
+// matrix is read and written once per 256 columns.  All arithmetic is FP64;
+// the upper triangle of A is not referenced.  The setup step of the
+// estimator (Section 3.3: the Cholesky factor of the covariance, then
+// tile-wise compression) runs on these kernels.
 #include "device_math.hpp"
 #include "internal.hpp"
 
@@ -88,19 +93,16 @@ __global__ __launch_bounds__(256) void k_chol_trsm(double *A, int64_t lda, int64
   }
 }
 
-// Trailing update of the lower tiles of A22 = A(k0+64:, k0+64:): tile
-// (ti, tj), ti >= tj, of nt x nt; each of the four waves computes one
-// 32 x 32 quarter as 2 x 2 matrix-core tiles of 16 x 16 over the 64
-// columns of the panel.  Operand layouts (as for the sweep's block
-// products): A operand lane l = row l % 16, column 4 k + l / 16; B operand
-// lane l = column l % 16 (a row of the panel), k-row 4 k + l / 16; the
-// result lane l holds rows l / 16 + 4 r, column l % 16.
+// Update of the lower tiles of A22 = A(k0+64:, k0+64:) in its first ntc
+// tile columns: tile (ti, tj) = (blockIdx.x, blockIdx.y), ti >= tj, of 64 x
+// 64; each of the four waves computes one 32 x 32 quarter as 2 x 2
+// matrix-core tiles of 16 x 16 over the 64 columns of the block.  Operand
+// layouts (as for the sweep's block products): A operand lane l = row l % 16,
+// column 4 k + l / 16; B operand lane l = column l % 16 (a row of the panel),
+// k-row 4 k + l / 16; the result lane l holds rows l / 16 + 4 r, column l % 16.
 __global__ __launch_bounds__(256) void k_chol_syrk(double *A, int64_t lda, int64_t n, int64_t k0) {
-  const int64_t tile = blockIdx.x;
-  int ti = static_cast<int>((sqrt(8.0 * static_cast<double>(tile) + 1.0) - 1.0) * 0.5);
-  while (static_cast<int64_t>(ti) * (ti + 1) / 2 > tile) --ti;
-  while (static_cast<int64_t>(ti + 1) * (ti + 2) / 2 <= tile) ++ti;
-  const int tj = static_cast<int>(tile - static_cast<int64_t>(ti) * (ti + 1) / 2);
+  const int ti = static_cast<int>(blockIdx.x), tj = static_cast<int>(blockIdx.y);
+  if (ti < tj) return;  // the whole group
   const int w = static_cast<int>(threadIdx.x) >> 6, l = static_cast<int>(threadIdx.x) & 63;
   const int64_t base = k0 + CB;
   const int64_t r0 = base + static_cast<int64_t>(ti) * CB + (w >> 1) * 32;
@@ -137,17 +139,116 @@ __global__ __launch_bounds__(256) void k_chol_syrk(double *A, int64_t lda, int64
       }
 }
 
+
+// Trailing update A(k1:, k1:) -= P P^T with P = A(k1:, k0:k1), k1 = k0 + 256:
+// lower tile (ti, tj) of 128 x 128, numbered by rows of the lower triangle.
+// The 128-row operand blocks of P go through LDS 16 columns at a time,
+// double-buffered (the next chunk's global loads are in flight during the
+// current chunk's products), stored k-major (row contiguous).  Wave w
+// computes the 64 x 64 block (w / 2, w % 2) as 4 x 4 matrix-core tiles (same
+// operand layouts as above); on a diagonal tile the wave of the strictly
+// upper block loads and synchronises but computes nothing.
+__global__ __launch_bounds__(256) void k_chol_wide(double *A, int64_t lda, int64_t n, int64_t k0) {
+  constexpr int PW = kCholPanel, KC = 16, TR = 128, LP = TR + 4;
+  __shared__ double As[2][KC][LP], Bs[2][KC][LP];
+  const int64_t tile = blockIdx.x;
+  int ti = static_cast<int>((sqrt(8.0 * static_cast<double>(tile) + 1.0) - 1.0) * 0.5);
+  while (static_cast<int64_t>(ti) * (ti + 1) / 2 > tile) --ti;
+  while (static_cast<int64_t>(ti + 1) * (ti + 2) / 2 <= tile) ++ti;
+  const int tj = static_cast<int>(tile - static_cast<int64_t>(ti) * (ti + 1) / 2);
+  const int t = static_cast<int>(threadIdx.x), w = t >> 6, l = t & 63;
+  const bool idle = ti == tj && (w >> 1) < (w & 1);
+  const int64_t base = k0 + PW;
+  const int64_t ra0 = base + static_cast<int64_t>(ti) * TR, rb0 = base + static_cast<int64_t>(tj) * TR;
+  // loader: thread t moves row t % 128 of columns t / 128 + 2 j, j < 8
+  const int lr = t & (TR - 1), lc = t >> 7;
+  const bool oka = ra0 + lr < n, okb = rb0 + lr < n;
+  const uint32_t ua = oka ? static_cast<uint32_t>(ra0 + lr) : 0u;  // out-of-range rows read row 0, store zero
+  const uint32_t ub = okb ? static_cast<uint32_t>(rb0 + lr) : 0u;
+  const double *Pl = A + (k0 + lc) * lda;
+  double ga[KC / 2], gb[KC / 2];
+  auto gload = [&](int ch) {
+#pragma unroll
+    for (int j = 0; j < KC / 2; ++j) {
+      const auto Pc = as_global(Pl + static_cast<int64_t>(ch * KC + 2 * j) * lda);
+      ga[j] = Pc[ua];
+      gb[j] = Pc[ub];
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < KC / 2; ++j) {
+      As[buf][lc + 2 * j][lr] = oka ? ga[j] : 0.0;
+      Bs[buf][lc + 2 * j][lr] = okb ? gb[j] : 0.0;
+    }
+  };
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int si = 0; si < 4; ++si)
+#pragma unroll
+    for (int sj = 0; sj < 4; ++sj) acc[si][sj] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int wa = (w >> 1) * 64 + (l & 15), wb = (w & 1) * 64 + (l & 15), kl = l >> 4;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+#pragma unroll 1
+  for (int ch = 0; ch < PW / KC; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < PW / KC) gload(ch + 1);
+    if (!idle) {
+#pragma unroll
+      for (int kk = 0; kk < KC / 4; ++kk) {
+        double va[4], vb[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          va[s] = As[buf][4 * kk + kl][wa + 16 * s];
+          vb[s] = Bs[buf][4 * kk + kl][wb + 16 * s];
+        }
+#pragma unroll
+        for (int si = 0; si < 4; ++si)
+#pragma unroll
+          for (int sj = 0; sj < 4; ++sj)
+            acc[si][sj] = __builtin_amdgcn_mfma_f64_16x16x4f64(va[si], vb[sj], acc[si][sj], 0, 0, 0);
+      }
+    }
+    if (ch + 1 < PW / KC) sstore(buf ^ 1);
+    __syncthreads();
+  }
+  if (idle) return;
+  const int64_t r0 = ra0 + (w >> 1) * 64, c0 = rb0 + (w & 1) * 64;
+#pragma unroll
+  for (int si = 0; si < 4; ++si)
+#pragma unroll
+    for (int sj = 0; sj < 4; ++sj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = r0 + si * 16 + (l >> 4) + 4 * r, col = c0 + sj * 16 + (l & 15);
+        if (row < n && col < n && row >= col) A[col * lda + row] -= acc[si][sj][r];
+      }
+}
+
 }  // namespace
 
 void launch_cholesky(hipStream_t s, double *A, int64_t lda, int64_t n, int32_t *info, double *scratch) {
-  for (int64_t k0 = 0; k0 < n; k0 += CB) {
-    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, A, lda, n, k0, info, scratch);
-    const int64_t rest = n - k0 - CB;
-    if (rest <= 0) break;
-    hipLaunchKernelGGL(k_chol_trsm, dim3(static_cast<unsigned>((rest + 255) / 256)), dim3(256), 0, s, A, lda, n, k0,
-                       scratch);
-    const int64_t nt = (rest + CB - 1) / CB;
-    hipLaunchKernelGGL(k_chol_syrk, dim3(static_cast<unsigned>(nt * (nt + 1) / 2)), dim3(256), 0, s, A, lda, n, k0);
+  for (int64_t K0 = 0; K0 < n; K0 += kCholPanel) {
+    const int64_t K1 = std::min<int64_t>(n, K0 + kCholPanel);
+    for (int64_t k0 = K0; k0 < K1; k0 += CB) {
+      hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, s, A, lda, n, k0, info, scratch);
+      const int64_t rest = n - k0 - CB;
+      if (rest <= 0) break;
+      hipLaunchKernelGGL(k_chol_trsm, dim3(static_cast<unsigned>((rest + 255) / 256)), dim3(256), 0, s, A, lda, n, k0,
+                         scratch);
+      // the panel's remaining columns (all rows below them)
+      const int64_t ntc = (K1 - (k0 + CB) + CB - 1) / CB;
+      if (ntc > 0)
+        hipLaunchKernelGGL(k_chol_syrk, dim3(static_cast<unsigned>((rest + CB - 1) / CB), static_cast<unsigned>(ntc)),
+                           dim3(256), 0, s, A, lda, n, k0);
+    }
+    const int64_t rest = n - K1;
+    if (rest > 0) {
+      const int64_t nt = (rest + 127) / 128;
+      hipLaunchKernelGGL(k_chol_wide, dim3(static_cast<unsigned>(nt * (nt + 1) / 2)), dim3(256), 0, s, A, lda, n, K0);
+    }
   }
 }
 
