@@ -17,6 +17,7 @@
 // tile-wise compression) runs on these kernels.
 #include "device_math.hpp"
 #include "internal.hpp"
+#include "setup_kernels.hpp"
 
 namespace tlrqmc {
 

@@ -18,6 +18,7 @@
 // factor is the same bit for bit from run to run.
 #include "device_math.hpp"
 #include "internal.hpp"
+#include "setup_kernels.hpp"
 
 namespace tlrqmc {
 

@@ -29,6 +29,7 @@
 #include <omp.h>
 
 #include "internal.hpp"
+#include "setup_kernels.hpp"
 
 namespace tlrqmc {
 

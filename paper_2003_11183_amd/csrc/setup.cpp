@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "setup_kernels.hpp"
 
 namespace tlrqmc {
 
