@@ -43,9 +43,9 @@ constexpr int64_t kSlotSamples = 32768;
 constexpr int64_t kSlotBytes = int64_t{2} << 30;
 // Active slots per step (descriptor capacity of one step).
 constexpr int kMaxSlots = 64;
-// Requests set up concurrently: one's Cholesky on the device overlaps the
-// host compression and layout of the others.
-constexpr int kSetupWorkers = 3;
+// Requests set up concurrently: one's device work (Cholesky, compression)
+// overlaps the host ordering and layout of the others.
+constexpr int kSetupWorkers = 4;
 constexpr int64_t kAlign = 256;
 
 // Device arena: one allocation from the caller's allocator, carved by best
