@@ -7,12 +7,14 @@
 // V_ij^T y_j.  Those images are produced right after tile j by one product
 // with V_panel(j) = [V_j+1,j ... V_r-1,j]; zmap sends each of its columns
 // to the row of Z_row(i) it belongs to.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <memory>
 #include <numeric>
 
 #include "internal.hpp"
+#include "setup_kernels.hpp"
 
 namespace tlrqmc {
 
@@ -36,9 +38,13 @@ void split_bf16(double x, unsigned short &hi, unsigned short &lo) {
 
 }  // namespace
 
-int factor_build(tlrqmc_ctx *ctx, int64_t n, int m, const int32_t *perm, const double *diag,
-                 const int32_t *ranks, const double *U, const double *V, int cap_hits,
-                 tlrqmc_factor **out) {
+namespace {
+
+// own_*: when given with the sizes the ranks imply, the host exchange copies
+// are taken from these vectors (left empty) instead of copied.
+int build_impl(tlrqmc_ctx *ctx, int64_t n, int m, const int32_t *perm, const double *diag, const int32_t *ranks,
+               const double *U, const double *V, int cap_hits, std::vector<double> *own_diag,
+               std::vector<double> *own_U, std::vector<double> *own_V, tlrqmc_factor **out) {
   if (!ctx || !out) return fail(TLRQMC_EINVAL, "null context or output pointer");
   *out = nullptr;
   if (n < 1 || m < 1) return fail(TLRQMC_EINVAL, "n and m must be positive (n=%lld, m=%d)",
@@ -97,24 +103,39 @@ int factor_build(tlrqmc_ctx *ctx, int64_t n, int m, const int32_t *perm, const d
   // host exchange copies (validated)
   int64_t diag_doubles = 0;
   for (int i = 0; i < r; ++i) diag_doubles += static_cast<int64_t>(f->tm[i]) * f->tm[i];
-  f->h_diag.assign(diag, diag + diag_doubles);
-  if (uv_doubles_u) {
-    f->h_U.assign(U, U + uv_doubles_u);
-    f->h_V.assign(V, V + uv_doubles_v);
+  if (own_diag && static_cast<int64_t>(own_diag->size()) == diag_doubles && own_U &&
+      static_cast<int64_t>(own_U->size()) == uv_doubles_u && own_V &&
+      static_cast<int64_t>(own_V->size()) == uv_doubles_v) {
+    f->h_diag.swap(*own_diag);
+    f->h_U.swap(*own_U);
+    f->h_V.swap(*own_V);
+  } else {
+    f->h_diag.assign(diag, diag + diag_doubles);
+    if (uv_doubles_u) {
+      f->h_U.assign(U, U + uv_doubles_u);
+      f->h_V.assign(V, V + uv_doubles_v);
+    }
   }
   {
-    int64_t o = 0;
+    std::vector<int64_t> o(r + 1, 0);
+    for (int i = 0; i < r; ++i) o[i + 1] = o[i] + static_cast<int64_t>(f->tm[i]) * f->tm[i];
+    // per tile: 0 = valid, 1 = non-finite entry, 2 + t = non-positive pivot t
+    std::vector<int64_t> verdict(r, 0);
+#pragma omp parallel for schedule(dynamic, 1)
     for (int i = 0; i < r; ++i) {
       const int mi = f->tm[i];
-      for (int t = 0; t < mi; ++t) {
-        for (int u = 0; u <= t; ++u) {
-          const double v = f->h_diag[o + static_cast<int64_t>(t) * mi + u];
-          if (!std::isfinite(v)) return fail(TLRQMC_EINVAL, "non-finite diagonal-tile entry in tile %d", i);
-        }
-        if (!(f->h_diag[o + static_cast<int64_t>(t) * mi + t] > 0.0))
-          return fail(TLRQMC_EINVAL, "diagonal entry %lld is not positive", static_cast<long long>(f->toff[i] + t));
+      const double *D = f->h_diag.data() + o[i];
+      for (int t = 0; t < mi && !verdict[i]; ++t) {
+        for (int u = 0; u <= t; ++u)
+          if (!std::isfinite(D[static_cast<int64_t>(t) * mi + u])) verdict[i] = 1;
+        if (!verdict[i] && !(D[static_cast<int64_t>(t) * mi + t] > 0.0)) verdict[i] = 2 + t;
       }
-      o += static_cast<int64_t>(mi) * mi;
+    }
+    for (int i = 0; i < r; ++i) {
+      if (verdict[i] == 1) return fail(TLRQMC_EINVAL, "non-finite diagonal-tile entry in tile %d", i);
+      if (verdict[i] >= 2)
+        return fail(TLRQMC_EINVAL, "diagonal entry %lld is not positive",
+                    static_cast<long long>(f->toff[i] + verdict[i] - 2));
     }
     int bad = 0;
     const int64_t nu = static_cast<int64_t>(f->h_U.size()), nv = static_cast<int64_t>(f->h_V.size());
@@ -319,6 +340,20 @@ int factor_build(tlrqmc_ctx *ctx, int64_t n, int m, const int32_t *perm, const d
   }
   *out = guard.release();
   return TLRQMC_OK;
+}
+
+}  // namespace
+
+int factor_build(tlrqmc_ctx *ctx, int64_t n, int m, const int32_t *perm, const double *diag,
+                 const int32_t *ranks, const double *U, const double *V, int cap_hits,
+                 tlrqmc_factor **out) {
+  return build_impl(ctx, n, m, perm, diag, ranks, U, V, cap_hits, nullptr, nullptr, nullptr, out);
+}
+
+int factor_build_take(tlrqmc_ctx *ctx, int64_t n, int m, const int32_t *perm, std::vector<double> &diag,
+                      const int32_t *ranks, std::vector<double> &U, std::vector<double> &V, int cap_hits,
+                      tlrqmc_factor **out) {
+  return build_impl(ctx, n, m, perm, diag.data(), ranks, U.data(), V.data(), cap_hits, &diag, &U, &V, out);
 }
 
 }  // namespace tlrqmc

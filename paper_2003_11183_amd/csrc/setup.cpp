@@ -499,6 +499,7 @@ int compress_build_device(tlrqmc_ctx *ctx, double *A, int64_t lda, int64_t n, in
     if (!ok || hipStreamSynchronize(s) != hipSuccess) return fail(TLRQMC_EDEVICE, "copy of the diagonal tiles failed");
   }
   std::vector<double> hdiag(doff[r]);
+#pragma omp parallel for schedule(dynamic, 1)
   for (int i = 0; i < r; ++i)
     for (int t = 0; t < tm[i]; ++t)
       for (int u = 0; u < tm[i]; ++u)
@@ -507,8 +508,17 @@ int compress_build_device(tlrqmc_ctx *ctx, double *A, int64_t lda, int64_t n, in
   const auto t_cp = clk::now();
   phase[1] += secs(t_dl, t_cp);
   std::vector<int32_t> ranks(static_cast<size_t>(r) * r, 0);
-  std::vector<std::vector<double>> Us(static_cast<size_t>(ntiles)), Vs(static_cast<size_t>(ntiles));
+  // U and V of each tile: in the copy of its batch's packed output (batch,
+  // offset of U, offset of V), or in a vector of its own when compressed on
+  // the host
+  std::vector<std::vector<double>> batch_uv;
+  struct Src {
+    int32_t batch = -1;
+    int64_t uo = 0, vo = 0;
+  };
+  std::vector<Src> src(static_cast<size_t>(ntiles));
   std::vector<int64_t> left;  // tiles for the host
+  std::vector<std::vector<double>> Ul, Vl;
   int cap_hits = 0;
   for (int64_t t0 = 0; t0 < ntiles; t0 += B) {
     const int count = static_cast<int>(std::min<int64_t>(B, ntiles - t0));
@@ -537,6 +547,8 @@ int compress_build_device(tlrqmc_ctx *ctx, double *A, int64_t lda, int64_t n, in
           hipStreamSynchronize(s) != hipSuccess)
         return fail(TLRQMC_EDEVICE, "copy of the compressed tiles failed");
     }
+    const int32_t bi = static_cast<int32_t>(batch_uv.size());
+    batch_uv.emplace_back(hOut, hOut + ut + vt);
     int64_t uo = 0, vo = ut;
     for (int q = 0; q < count; ++q) {
       const int64_t t = t0 + q;
@@ -551,8 +563,7 @@ int compress_build_device(tlrqmc_ctx *ctx, double *A, int64_t lda, int64_t n, in
       const int k = hInfo[4 * q + 1];
       ranks[static_cast<size_t>(i) * r + j] = k;
       cap_hits += (hInfo[4 * q + 2] & 2) ? 1 : 0;
-      Us[t].assign(hOut + uo, hOut + uo + static_cast<int64_t>(mi) * k);
-      Vs[t].assign(hOut + vo, hOut + vo + static_cast<int64_t>(mj) * k);
+      src[t] = {bi, uo, vo};
       uo += static_cast<int64_t>(mi) * k;
       vo += static_cast<int64_t>(mj) * k;
     }
@@ -575,27 +586,52 @@ int compress_build_device(tlrqmc_ctx *ctx, double *A, int64_t lda, int64_t n, in
       if (!ok || hipStreamSynchronize(s) != hipSuccess) return fail(TLRQMC_EDEVICE, "copy of the factor failed");
     }
     int hits = 0;
+    Ul.resize(left.size());
+    Vl.resize(left.size());
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : hits)
     for (size_t q = 0; q < left.size(); ++q) {
       int64_t r0, c0;
       int mi, mj;
       compress_tile_at(left[q], n, m, r0, c0, mi, mj);
       bool capped = false;
-      const int k = compress_tile(hT + q * per, mi, mi, mj, tol, max_rank, Us[left[q]], Vs[left[q]], capped);
+      const int k = compress_tile(hT + q * per, mi, mi, mj, tol, max_rank, Ul[q], Vl[q], capped);
       ranks[static_cast<size_t>(r0 / m) * r + c0 / m] = k;
       hits += capped ? 1 : 0;
     }
     cap_hits += hits;
+    for (size_t q = 0; q < left.size(); ++q) src[left[q]].batch = -2 - static_cast<int32_t>(q);
   }
   phase[2] += secs(t_cp, clk::now());
   Aguard.reset();
   const auto t_layout = clk::now();
-  std::vector<double> hU, hV;
+  // the exchange arrays, tiles in row order, filled in parallel
+  std::vector<int64_t> uoff(ntiles + 1, 0), voff(ntiles + 1, 0);
   for (int64_t t = 0; t < ntiles; ++t) {
-    hU.insert(hU.end(), Us[t].begin(), Us[t].end());
-    hV.insert(hV.end(), Vs[t].begin(), Vs[t].end());
+    int64_t r0, c0;
+    int mi, mj;
+    compress_tile_at(t, n, m, r0, c0, mi, mj);
+    const int64_t k = ranks[static_cast<size_t>(r0 / m) * r + c0 / m];
+    uoff[t + 1] = uoff[t] + mi * k;
+    voff[t + 1] = voff[t] + mj * k;
   }
-  int st = factor_build(ctx, n, m, p.data(), hdiag.data(), ranks.data(), hU.data(), hV.data(), cap_hits, out);
+  std::vector<double> hU(uoff[ntiles]), hV(voff[ntiles]);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t t = 0; t < ntiles; ++t) {
+    const Src &e = src[t];
+    const int64_t nu = uoff[t + 1] - uoff[t], nv = voff[t + 1] - voff[t];
+    const double *su, *sv;
+    if (e.batch >= 0) {
+      su = batch_uv[e.batch].data() + e.uo;
+      sv = batch_uv[e.batch].data() + e.vo;
+    } else {
+      su = Ul[-2 - e.batch].data();
+      sv = Vl[-2 - e.batch].data();
+    }
+    if (nu) std::memcpy(hU.data() + uoff[t], su, nu * sizeof(double));
+    if (nv) std::memcpy(hV.data() + voff[t], sv, nv * sizeof(double));
+  }
+  std::vector<std::vector<double>>().swap(batch_uv);
+  int st = factor_build_take(ctx, n, m, p.data(), hdiag, ranks.data(), hU, hV, cap_hits, out);
   if (st) return st;
   phase[3] = secs(t_layout, clk::now());
   for (int k = 0; k < 4; ++k) (*out)->setup_seconds[k] = phase[k];

@@ -1,12 +1,17 @@
-// Launchers of the setup kernels (dense Cholesky, tile compression) and the
-// sizes of their buffers.  Kept apart from internal.hpp, which the estimator
-// kernels include.
+// Setup-side declarations: launchers of the setup kernels (dense Cholesky,
+// tile compression), the sizes of their buffers, and factor assembly from
+// vectors the factor takes over.  Kept apart from internal.hpp, which the
+// estimator kernels include.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstdint>
+#include <vector>
+
+struct tlrqmc_ctx;
+struct tlrqmc_factor;
 
 namespace tlrqmc {
 
@@ -45,5 +50,12 @@ inline int64_t compress_scratch_bytes(int64_t n, int m) {
   if (m > kCmpMaxTile) return 0;
   return compress_batch_tiles(n, m) * compress_slot_bytes(m) + 4 * 256;
 }
+
+// factor_build (factor.cpp) taking diag, U and V over instead of copying
+// them when their sizes are those the ranks imply (the vectors may then be
+// left empty); arguments otherwise as for factor_build.
+int factor_build_take(tlrqmc_ctx *ctx, int64_t n, int m, const int32_t *perm, std::vector<double> &diag,
+                      const int32_t *ranks, std::vector<double> &U, std::vector<double> &V, int cap_hits,
+                      tlrqmc_factor **out);
 
 }  // namespace tlrqmc
