@@ -7,7 +7,9 @@ fall either way), and V has orthonormal columns.
 Cases: ragged last tile row (n = 2025, m = 128), a 512-wide tile with a
 ragged row count (seven rows per lane in the QR kernel), and a tolerance so
 small that some tiles need more QR steps than the device kernels hold:
-those are compressed on the host, and the factor says how many.
+those are compressed on the host, and the factor says how many.  Degenerate
+cases: a one-row last tile, a tolerance above every tile's norm (all ranks
+zero), and tiles of 64 and of 512 with a short last row of tiles.
 """
 
 import numpy as np
@@ -30,9 +32,9 @@ def ctx(T):
     return T.Context(0)
 
 
-def check_factor(T, ctx, g, beta, m, tol, cap=0):
-    xy = synth.grid_xy(g)
-    n = g * g
+def check_factor(T, ctx, g, beta, m, tol, cap=0, xy=None):
+    xy = synth.grid_xy(g) if xy is None else xy
+    n = len(xy)
     F = T.Factor.build(ctx, {"xy": xy, "beta": beta}, n, m, tol, cap)
     st = F.stats()
     perm, diag, ranks, U, V = F.export()
@@ -91,3 +93,22 @@ def test_device_compression_is_reproducible(T, ctx):
         sums.append(F.stats()["checksum"])
         F.free()
     assert sums[0] == sums[1]
+
+
+def test_device_compression_one_row_tile(T, ctx):
+    # n = 129, m = 128: the only off-diagonal tile is 1 x 128
+    st = check_factor(T, ctx, 0, 0.1, 128, 1e-5, xy=synth.grid_xy(12)[:129])
+    assert st["r"] == 2 and st["host_tiles"] == 0
+
+
+def test_device_compression_all_ranks_zero(T, ctx):
+    # tolerance above every tile's norm: every off-diagonal tile has rank 0
+    st = check_factor(T, ctx, 32, 0.1, 128, 10.0)
+    assert st["k_tot"] == 0 and st["host_tiles"] == 0
+
+
+@pytest.mark.parametrize("m", [64, 512])
+def test_device_compression_short_last_tile_row(T, ctx, m):
+    # n = 600: last tile row of 24 rows (m = 64) or 88 rows (m = 512)
+    st = check_factor(T, ctx, 0, 0.3, m, 1e-3, xy=synth.grid_xy(25)[:600])
+    assert st["host_tiles"] == 0
