@@ -7,6 +7,8 @@ concurrently, that admission defers a request until memory is returned, and
 that requests that cannot fit or are invalid are refused.
 """
 
+import time
+
 import numpy as np
 import pytest
 
@@ -79,7 +81,13 @@ def test_server_result_same_alone_and_in_mix(ctx):
     S = T.Server(ctx, 8 << 30)
     try:
         alone = [S.result(submit(S, r), timeout_s=120) for r in MIX]
-        tickets = [submit(S, r) for r in MIX]
+        # the long first request is running before the others arrive (their
+        # setups may otherwise finish, and their runs end, before it starts)
+        tickets = [submit(S, MIX[0])]
+        t_end = time.monotonic() + 60
+        while S.stats()["running"] == 0 and time.monotonic() < t_end:
+            time.sleep(0.001)
+        tickets += [submit(S, r) for r in MIX[1:]]
         mixed = [S.result(t, timeout_s=120) for t in tickets]
         st = S.stats()
     finally:
