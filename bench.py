@@ -58,15 +58,20 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_work(kind: str, st: dict, n: int, m: int, precision: int) -> tuple[float, str]:
-    """Algorithmic work per sample of all launches of one kernel kind, and its bound."""
+def kernel_work(kind: str, st: dict, n: int, m: int, precision: int) -> tuple[float, str, float]:
+    """Algorithmic work per sample of all launches of one kernel kind, its
+    bound and the peak of that bound: the precision form's low-rank products
+    run on BF16 matrix cores, the FP64 form's limit update on FP64 matrix
+    cores and its projection on the FP64 vector ALU (both 78.6 TFLOP/s)."""
     if kind == "sweep":
         tri = sum(min(m, n - i * m) * (min(m, n - i * m) - 1) for i in range((n + m - 1) // m))
-        return tri + C_PHI * n, "alu"
+        return tri + C_PHI * n, "alu", PEAK_FP64_VALU
     if kind in ("delta", "zproj"):
         f = 2.0 * m * st["k_tot"]
-        return (3 * f, "mfma") if precision == 1 else (f, "alu")
-    return float("nan"), "alu"
+        if precision == 1:
+            return 3 * f, "mfma", PEAK_BF16_MFMA
+        return f, ("mfma" if kind == "delta" else "alu"), PEAK_FP64_VALU
+    return float("nan"), "alu", PEAK_FP64_VALU
 
 
 def time_form(T, ctx, F, c, precision, steps, warmup):
@@ -97,11 +102,16 @@ def time_form(T, ctx, F, c, precision, steps, warmup):
 # only while the kernel sources and the build script (its device flags) still
 # have the digest it was measured on.
 TRAFFIC = {
-    (3, "sweep", 1): {"bytes_per_launch": 1.933e9, "digest": "1d2491106061a0e9"},
-    (3, "delta", 0): {"bytes_per_launch": 1.175e9, "digest": "1d2491106061a0e9"},
+    (3, "sweep", 1): {"bytes_per_launch": 1.933e9, "digest": "d03600bba52cbdef"},
+    (3, "delta", 1): {"bytes_per_launch": 4.352e8, "digest": "d03600bba52cbdef"},
+    (3, "zproj", 1): {"bytes_per_launch": 4.30e8, "digest": "d03600bba52cbdef"},
+    (3, "sweep", 0): {"bytes_per_launch": 3.856e9, "digest": "d03600bba52cbdef"},
+    (3, "delta", 0): {"bytes_per_launch": 1.304e9, "digest": "d03600bba52cbdef"},
+    (3, "zproj", 0): {"bytes_per_launch": 2.414e9, "digest": "d03600bba52cbdef"},
 }
 KERNEL_SOURCES = tuple(os.path.join("csrc", f) for f in (
-    "kernels.hip", "kernels_mfma.hip", "device_math.hpp", "special_tables.hpp", "internal.hpp")) + ("build.py",)
+    "kernels.hip", "kernels_mfma.hip", "kernels_lr64.hip", "device_math.hpp", "special_tables.hpp",
+    "internal.hpp")) + ("build.py",)
 
 
 def kernel_digest() -> str:
@@ -124,13 +134,12 @@ def roofline_of(T, results, st, c, precision, steps):
     kb = {k: sum(r["kernel_busy_seconds"][k] for r in results) for k in T.KERNEL_NAMES}
     kl = {k: sum(r["kernel_launches"][k] for r in results) for k in T.KERNEL_NAMES}
     dom = max(kb, key=kb.get)
-    work, bound = kernel_work(dom, st, n, m, precision)
+    work, bound, peak = kernel_work(dom, st, n, m, precision)
     launches = max(kl[dom], 1)
     per_launch = work * samples * steps / launches
     avg = ks[dom] / launches
     achieved = per_launch / avg
     chip = work * samples * steps / kb[dom]
-    peak = PEAK_BF16_MFMA if bound == "mfma" else PEAK_FP64_VALU
     tr = TRAFFIC.get((c["id"], dom, precision))
     traffic = tr["bytes_per_launch"] if tr and tr["digest"] == kernel_digest() else None
     return {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",

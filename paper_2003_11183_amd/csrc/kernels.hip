@@ -8,9 +8,11 @@
 //
 // Per diagonal tile j (Section 3.4, TLR QMC for MVN: the dense MVN step on
 // B_j after the limits of tile j were updated by the earlier tiles):
-//   k_delta_f64 : Delta_j = U_row(j) Z_row(j)   (low-rank limit update)
+//   limit update: Delta_j = U_row(j) Z_row(j)  (FP64 matrix cores in
+//                 kernels_lr64.hip; precision form in kernels_mfma.hip)
 //   k_sweep     : the SOV recursion over the rows of B_j (Section 2.1, Eq. 2)
-//   k_zproj_f64 : Z(:, j) = V_panel(j)^T Y_j    (rank-space image of y_j)
+//   k_zproj_f64 : Z(:, j) = V_panel(j)^T Y_j    (rank-space image of y_j;
+//                 precision form in kernels_mfma.hip)
 // and k_reduce combines log P per shift (Section 2.1: mean over samples).
 #include <type_traits>
 
@@ -235,38 +237,6 @@ __global__ __launch_bounds__(256) void k_sweep_batch(const SweepParams *ps) {
 }
 
 // ------------------------------------------------------- low rank, FP64 ----
-// Delta(t, s) = sum_q U_row(t, q) Z(q, s) for 64 rows t per block row.
-// U_row is column-major with leading dimension lda (rows padded with zeros).
-__device__ __forceinline__ void delta_f64_body(const LrParams &p, int64_t si, int t0) {
-  if (si >= p.count || t0 >= p.rows) return;
-  double acc[kLrRows];
-#pragma unroll
-  for (int t = 0; t < kLrRows; ++t) acc[t] = 0.0;
-  const double *Z = p.In + si;
-  const auto U = as_const(p.Mat + t0);
-#pragma unroll 2
-  for (int q = 0; q < p.K; ++q) {
-    const double z = Z[static_cast<int64_t>(q) * p.ld];
-    const auto Uq = U + static_cast<int64_t>(q) * p.lda;
-#pragma unroll
-    for (int t = 0; t < kLrRows; ++t) acc[t] = fma(Uq[t], z, acc[t]);
-  }
-  double *O = p.Out + si;
-  const int nr = min(kLrRows, p.rows - t0);
-#pragma unroll
-  for (int t = 0; t < kLrRows; ++t)
-    if (t < nr) O[static_cast<int64_t>(t0 + t) * p.ld] = acc[t];
-}
-
-__global__ __launch_bounds__(256) void k_delta_f64(LrParams p) {
-  delta_f64_body(p, static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x, blockIdx.y * kLrRows);
-}
-
-__global__ __launch_bounds__(256) void k_delta_f64_batch(const LrParams *ps) {
-  const LrParams p = load_uniform(ps + blockIdx.z);
-  delta_f64_body(p, static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x, blockIdx.y * kLrRows);
-}
-
 // Z(map(c), s) = sum_t V_panel(t, c) Y(t, s) for 64 columns c per block row.
 // V_panel is row-major with leading dimension lda (columns padded with zeros).
 __device__ __forceinline__ void zproj_f64_body(const LrParams &p, int64_t si, int c0) {
@@ -384,11 +354,6 @@ void launch_sweep(hipStream_t s, const SweepParams &p, bool two_sided, bool scal
   }
 }
 
-void launch_delta_f64(hipStream_t s, const LrParams &p) {
-  const dim3 grid(grid_of(p.count), static_cast<unsigned>((p.rows + kLrRows - 1) / kLrRows));
-  hipLaunchKernelGGL(k_delta_f64, grid, dim3(256), 0, s, p);
-}
-
 void launch_zproj_f64(hipStream_t s, const LrParams &p) {
   const dim3 grid(grid_of(p.count), static_cast<unsigned>((p.rows + kLrRows - 1) / kLrRows));
   hipLaunchKernelGGL(k_zproj_f64, grid, dim3(256), 0, s, p);
@@ -418,11 +383,6 @@ void launch_sweep_batch(hipStream_t s, const SweepParams *d, int n, int64_t max_
     if (scaled) sweep_batch_form<false, true>(s, d, grid, prec);
     else sweep_batch_form<false, false>(s, d, grid, prec);
   }
-}
-
-void launch_delta_f64_batch(hipStream_t s, const LrParams *d, int n, int64_t max_count, int max_rows) {
-  const dim3 grid(grid_of(max_count), static_cast<unsigned>((max_rows + kLrRows - 1) / kLrRows), n);
-  hipLaunchKernelGGL(k_delta_f64_batch, grid, dim3(256), 0, s, d);
 }
 
 void launch_zproj_f64_batch(hipStream_t s, const LrParams *d, int n, int64_t max_count, int max_rows) {
