@@ -142,13 +142,28 @@ def roofline_of(T, results, st, c, precision, steps):
     chip = work * samples * steps / kb[dom]
     tr = TRAFFIC.get((c["id"], dom, precision))
     traffic = tr["bytes_per_launch"] if tr and tr["digest"] == kernel_digest() else None
+    # the same figures for every kernel kind of the step (HBM rate from the
+    # measured traffic where it is current)
+    kinds = {}
+    for k in ("sweep", "delta", "zproj"):
+        if kl[k] == 0 or ks[k] <= 0:
+            continue
+        w_k, b_k, p_k = kernel_work(k, st, n, m, precision)
+        pl = w_k * samples * steps / kl[k]
+        av = ks[k] / kl[k]
+        t_k = TRAFFIC.get((c["id"], k, precision))
+        tb = t_k["bytes_per_launch"] if t_k and t_k["digest"] == kernel_digest() else None
+        kinds[k] = {"bound": b_k, "achieved": pl / av / 1e12, "peak": p_k / 1e12, "frac": pl / av / p_k,
+                    "avg_launch_ms": 1e3 * av, "traffic": tb,
+                    "hbm_tb_per_s": (tb / av / 1e12) if tb else None}
     return {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
             "frac": achieved / peak, "traffic": traffic, "traffic_unit": "bytes/launch",
             "kernel": dom, "work_per_launch_tflop": per_launch / 1e12, "avg_launch_ms": 1e3 * avg,
             "achieved_chip": chip / 1e12, "frac_chip": chip / peak,
             "busy_ms_per_step": {k: 1e3 * v / steps for k, v in kb.items()},
             "launch_ms_sum_per_step": {k: 1e3 * v / steps for k, v in ks.items()},
-            "launches_per_step": {k: kl[k] // steps for k in kl}}
+            "launches_per_step": {k: kl[k] // steps for k in kl},
+            "kinds": kinds}
 
 
 def main():
