@@ -10,7 +10,7 @@
 //                  block, on 64 x 64 tiles with FP64 matrix cores
 //                  (v_mfma_f64_16x16x4_f64);
 // then one update of the trailing matrix by the whole panel (k_chol_wide:
-// 128 x 128 tiles, 256-deep products on the matrix cores), so the trailing
+// 256 x 128 tiles, 256-deep products on the matrix cores), so the trailing
 // matrix is read and written once per 256 columns.  All arithmetic is FP64;
 // the upper triangle of A is not referenced.  The setup step of the
 // estimator (Section 3.3: the Cholesky factor of the covariance, then
@@ -141,47 +141,47 @@ __global__ __launch_bounds__(256) void k_chol_syrk(double *A, int64_t lda, int64
 }
 
 
-// Trailing update A(k1:, k1:) -= P P^T with P = A(k1:, k0:k1), k1 = k0 + 256:
-// lower tile (ti, tj) of 128 x 128, numbered by rows of the lower triangle.
-// The 128-row operand blocks of P go through LDS 16 columns at a time,
-// double-buffered (the next chunk's global loads are in flight during the
-// current chunk's products), stored k-major (row contiguous).  Wave w
-// computes the 64 x 64 block (w / 2, w % 2) as 4 x 4 matrix-core tiles (same
-// operand layouts as above); on a diagonal tile the wave of the strictly
-// upper block loads and synchronises but computes nothing.
-__global__ __launch_bounds__(256) void k_chol_wide(double *A, int64_t lda, int64_t n, int64_t k0) {
-  constexpr int PW = kCholPanel, KC = 16, TR = 128, LP = TR + 4;
-  __shared__ double As[2][KC][LP], Bs[2][KC][LP];
+// Trailing update A(k1:, k1:) -= P P^T with P = A(k1:, k0:k1), k1 = k0 + 256,
+// on 256 x 128 tiles of the lower triangle with eight waves: the tiles of
+// row block ti (256 rows) are the column blocks tj = 0 .. 2 ti + 1 (128
+// columns), so tile b is (ti, b - ti (ti + 1)) with ti the largest t such
+// that t (t + 1) <= b.  The two operand blocks of P (256 and 128 rows) go
+// through LDS 16 columns at a time, double-buffered (the next chunk's global
+// loads are in flight during the current chunk's products), stored k-major.
+// Wave w computes the 64 x 64 block (w / 2, w % 2) as 4 x 4 matrix-core
+// tiles (operand layouts as above); a wave whose block lies wholly above the
+// diagonal loads and synchronises but computes nothing.
+__global__ __launch_bounds__(512) void k_chol_wide(double *A, int64_t lda, int64_t n, int64_t k0) {
+  constexpr int PW = kCholPanel, KC = 16, RA = 256, RB = 128;
+  __shared__ double As[2][KC][RA + 4], Bs[2][KC][RB + 4];
   const int64_t tile = blockIdx.x;
-  int ti = static_cast<int>((sqrt(8.0 * static_cast<double>(tile) + 1.0) - 1.0) * 0.5);
-  while (static_cast<int64_t>(ti) * (ti + 1) / 2 > tile) --ti;
-  while (static_cast<int64_t>(ti + 1) * (ti + 2) / 2 <= tile) ++ti;
-  const int tj = static_cast<int>(tile - static_cast<int64_t>(ti) * (ti + 1) / 2);
+  int64_t ti = static_cast<int64_t>((sqrt(4.0 * static_cast<double>(tile) + 1.0) - 1.0) * 0.5);
+  while (ti * (ti + 1) > tile) --ti;
+  while ((ti + 1) * (ti + 2) <= tile) ++ti;
+  const int64_t tj = tile - ti * (ti + 1);
   const int t = static_cast<int>(threadIdx.x), w = t >> 6, l = t & 63;
-  const bool idle = ti == tj && (w >> 1) < (w & 1);
   const int64_t base = k0 + PW;
-  const int64_t ra0 = base + static_cast<int64_t>(ti) * TR, rb0 = base + static_cast<int64_t>(tj) * TR;
-  // loader: thread t moves row t % 128 of columns t / 128 + 2 j, j < 8
-  const int lr = t & (TR - 1), lc = t >> 7;
-  const bool oka = ra0 + lr < n, okb = rb0 + lr < n;
-  const uint32_t ua = oka ? static_cast<uint32_t>(ra0 + lr) : 0u;  // out-of-range rows read row 0, store zero
-  const uint32_t ub = okb ? static_cast<uint32_t>(rb0 + lr) : 0u;
-  const double *Pl = A + (k0 + lc) * lda;
-  double ga[KC / 2], gb[KC / 2];
+  const int64_t ra0 = base + ti * RA, rb0 = base + tj * RB;
+  const int64_t R0 = ra0 + (w >> 1) * 64, C0 = rb0 + (w & 1) * 64;
+  const bool idle = R0 + 63 < C0;
+  // loaders: A rows t % 256, columns t / 256 + 2 j (j < 8); B rows t % 128,
+  // columns t / 128 + 4 j (j < 4)
+  const int lra = t & (RA - 1), lca = t >> 8, lrb = t & (RB - 1), lcb = t >> 7;
+  const bool oka = ra0 + lra < n, okb = rb0 + lrb < n;
+  const uint32_t ua = oka ? static_cast<uint32_t>(ra0 + lra) : 0u;  // out-of-range rows read row 0, store zero
+  const uint32_t ub = okb ? static_cast<uint32_t>(rb0 + lrb) : 0u;
+  double ga[8], gb[4];
   auto gload = [&](int ch) {
 #pragma unroll
-    for (int j = 0; j < KC / 2; ++j) {
-      const auto Pc = as_global(Pl + static_cast<int64_t>(ch * KC + 2 * j) * lda);
-      ga[j] = Pc[ua];
-      gb[j] = Pc[ub];
-    }
+    for (int j = 0; j < 8; ++j) ga[j] = as_global(A + (k0 + ch * KC + lca + 2 * j) * lda)[ua];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) gb[j] = as_global(A + (k0 + ch * KC + lcb + 4 * j) * lda)[ub];
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int j = 0; j < KC / 2; ++j) {
-      As[buf][lc + 2 * j][lr] = oka ? ga[j] : 0.0;
-      Bs[buf][lc + 2 * j][lr] = okb ? gb[j] : 0.0;
-    }
+    for (int j = 0; j < 8; ++j) As[buf][lca + 2 * j][lra] = oka ? ga[j] : 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Bs[buf][lcb + 4 * j][lrb] = okb ? gb[j] : 0.0;
   };
   f64x4 acc[4][4];
 #pragma unroll
@@ -216,14 +216,13 @@ __global__ __launch_bounds__(256) void k_chol_wide(double *A, int64_t lda, int64
     __syncthreads();
   }
   if (idle) return;
-  const int64_t r0 = ra0 + (w >> 1) * 64, c0 = rb0 + (w & 1) * 64;
 #pragma unroll
   for (int si = 0; si < 4; ++si)
 #pragma unroll
     for (int sj = 0; sj < 4; ++sj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = r0 + si * 16 + (l >> 4) + 4 * r, col = c0 + sj * 16 + (l & 15);
+        const int64_t row = R0 + si * 16 + (l >> 4) + 4 * r, col = C0 + sj * 16 + (l & 15);
         if (row < n && col < n && row >= col) A[col * lda + row] -= acc[si][sj][r];
       }
 }
@@ -247,8 +246,8 @@ void launch_cholesky(hipStream_t s, double *A, int64_t lda, int64_t n, int32_t *
     }
     const int64_t rest = n - K1;
     if (rest > 0) {
-      const int64_t nt = (rest + 127) / 128;
-      hipLaunchKernelGGL(k_chol_wide, dim3(static_cast<unsigned>(nt * (nt + 1) / 2)), dim3(256), 0, s, A, lda, n, K0);
+      const int64_t nt = (rest + 255) / 256;
+      hipLaunchKernelGGL(k_chol_wide, dim3(static_cast<unsigned>(nt * (nt + 1))), dim3(512), 0, s, A, lda, n, K0);
     }
   }
 }
