@@ -50,11 +50,31 @@ __device__ __host__ inline TileAt tile_at(int64_t t, int64_t n, int m) {
   return a;
 }
 
-// Sum over the wave; every lane gets lane 0's value (one rounding for all).
+// DPP move of a double (both halves); lanes whose source is outside the
+// pattern or masked off read 0.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ inline double dpp_mov(double x) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(u & 0xffffffffu), CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(u >> 32), CTRL, ROW_MASK, 0xf, false);
+  return __builtin_bit_cast(double, (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) |
+                                        static_cast<uint32_t>(lo));
+}
+
+// Sum over the wave with DPP (no LDS traffic): sums within rows of 16 lanes
+// by row shifts 1, 2, 4, 8, then row broadcasts 15 and 31 carry the rows'
+// totals up; lane 63 holds the total, which every lane gets.
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return __shfl(v, 0);
+  v += dpp_mov<0x111>(v);        // row_shr:1
+  v += dpp_mov<0x112>(v);        // row_shr:2
+  v += dpp_mov<0x114>(v);        // row_shr:4
+  v += dpp_mov<0x118>(v);        // row_shr:8
+  v += dpp_mov<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_mov<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(u & 0xffffffffu), 63));
+  const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(u >> 32), 63));
+  return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
 }
 
 __device__ inline double wave_max(double v) {
