@@ -113,6 +113,45 @@ def test_random_tlr_ragged_chunked(T, ctx, two_sided, nu):
     assert_estimate_close(res, ref)
 
 
+@pytest.mark.parametrize("n,m,two_sided,nu", [(1, 64, False, 0.0), (1, 64, True, 0.0), (1, 64, True, 4.0),
+                                              (2, 64, True, 0.0), (17, 16, False, 6.0), (33, 16, True, 3.0)])
+def test_tiny_problems(T, ctx, n, m, two_sided, nu):
+    """One and two variables, and 16-row tiles (one row block each; a last
+    tile of one row).  Per sample against the oracle in the FP64 form, and
+    the precision form within 1e-4 max(1, |log P|).  Closed forms: with one
+    variable every normal sample equals Phi(b/d) - Phi(a/d), and the
+    Student-t estimate lies within the standard error of the t CDF
+    difference; with two, the normal estimate matches the bivariate normal
+    CDF (scipy, accurate to about 1e-5)."""
+    from scipy.special import ndtr
+    from scipy.stats import multivariate_normal, t as student_t
+    fac = synth.random_tlr_factor(n, m, seed=40 + n, rank_mean=3.0, rank_max=8, zero_frac=0.0)
+    rng = np.random.default_rng(n)
+    b = rng.uniform(-0.5, 2.0, n)
+    a = b - rng.uniform(0.5, 3.0, n) if two_sided else np.full(n, -np.inf)
+    perm = np.arange(n, dtype=np.int32)
+    N, M, seed = 500, 4, 21
+    res, ref, lg, lr = run_both(T, ctx, fac, perm, a, b, nu, N, M, seed)
+    assert_logp_close(lg, lr)
+    assert_estimate_close(res, ref)
+    F = T.Factor.from_tiles(ctx, n, m, fac[0], fac[1], fac[2], fac[3], perm)
+    r16 = T.probability(ctx, F, a, b, N, M, seed, nu=nu, precision=1, return_logp=True)
+    err = np.abs(r16["logp"] - lr) / np.maximum(1.0, np.abs(lr))
+    assert err.max() <= 1e-4, f"precision form: max scaled error {err.max():.2e}"
+    if n == 1:
+        d = fac[0][0][0, 0]
+        lo, hi = a[0] / d, b[0] / d
+        if nu == 0.0:
+            assert np.allclose(lg, math.log(ndtr(hi) - ndtr(lo)), rtol=1e-12, atol=0)
+        else:
+            p = student_t.cdf(hi, nu) - student_t.cdf(lo, nu)
+            assert abs(res["p"] - p) <= 4.0 * res["std_err"] + 1e-5 * p
+    if n == 2:
+        L = fac[0][0]
+        p = multivariate_normal.cdf(b, mean=np.zeros(2), cov=L @ L.T, lower_limit=a)
+        assert abs(res["p"] - p) <= 4.0 * res["std_err"] + 2e-5
+
+
 def test_exp_kernel_tlr_factor_n1024(T, ctx):
     fac, perm, _ = exp_factor(32, 0.1, 128, 1e-5)
     b = synth.upper_limits_uniform(1024, 2005)
