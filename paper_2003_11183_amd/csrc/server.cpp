@@ -45,7 +45,7 @@ constexpr int64_t kSlotBytes = int64_t{2} << 30;
 constexpr int kMaxSlots = 64;
 // Requests set up concurrently: one's device work (Cholesky, compression)
 // overlaps the host ordering and layout of the others.
-constexpr int kSetupWorkers = 4;
+constexpr int kSetupWorkers = 6;
 constexpr int64_t kAlign = 256;
 
 // Device arena: one allocation from the caller's allocator, carved by best
