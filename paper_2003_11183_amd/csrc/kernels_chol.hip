@@ -28,45 +28,72 @@ namespace {
 constexpr int CB = kCholBlock;
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-// Diagonal block at (k0, k0), b = min(64, n - k0) rows.  Right-looking over
-// its columns; thread t works on row t % 64 and on the columns of that row
-// congruent to t / 64 modulo 4.  On a non-positive pivot the global row
-// index + 1 goes to *info and every later block leaves at once.
+// Diagonal block at (k0, k0), b = min(64, n - k0) rows.  Right-looking
+// over its columns with the block in registers: thread t holds row
+// i = t % 64 at the columns congruent to g = t / 64 modulo 4 (wave g owns
+// those columns).  At column j the owning wave takes the pivot from lane j,
+// forms L(:, j) and publishes it in LDS (two buffers, alternating); after
+// one barrier every thread subtracts L(i, j) L(c, j) from each of its
+// entries.  Entries above the diagonal also receive these updates but are
+// never read or stored, and L(r, j) is published as zero for r <= j, so the
+// update needs no predicate.  Each entry sees the same fma updates in the
+// same order as an in-place factorization.  On a non-positive pivot the
+// global row index + 1 goes to *info and every later block leaves at once.
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const uint64_t u = static_cast<uint64_t>(__double_as_longlong(v));
+  const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(u & 0xffffffffu), lane));
+  const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(u >> 32), lane));
+  return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
+}
+
 __global__ __launch_bounds__(256) void k_chol_diag(double *A, int64_t lda, int64_t n, int64_t k0, int32_t *info,
                                                    double *scratch) {
-  __shared__ double a[CB][CB + 1];
+  __shared__ double col[2][CB];
+  __shared__ int bad;
   if (*info != 0) return;  // an earlier block failed (the same for the whole group)
   const int t = static_cast<int>(threadIdx.x);
-  const int i = t & (CB - 1), cg = t >> 6;
+  const int i = t & (CB - 1), g = t >> 6;
   const int b = static_cast<int>(min<int64_t>(CB, n - k0));
   double *D = A + k0 * lda + k0;
-  for (int c = cg; c < b; c += 4)
-    if (i < b && i >= c) a[i][c] = D[c * lda + i];
-  __syncthreads();
-  for (int j = 0; j < b; ++j) {
-    const double ajj = a[j][j];
-    if (!(ajj > 0.0)) {  // every thread reads the same value: a uniform exit
-      if (t == 0) *info = static_cast<int32_t>(k0 + j + 1);
-      return;
-    }
-    const double d = sqrt(ajj);
-    __syncthreads();
-    if (cg == 0 && i == j) a[j][j] = d;
-    if (cg == 0 && i > j && i < b) a[i][j] /= d;
-    __syncthreads();
-    if (i > j && i < b) {
-      const double lij = a[i][j];
-      for (int l = j + 1 + ((cg - (j + 1)) & 3); l <= i; l += 4) a[i][l] = fma(-lij, a[l][j], a[i][l]);
-    }
-    __syncthreads();
+  double r[CB / 4];
+#pragma unroll
+  for (int k = 0; k < CB / 4; ++k) {
+    const int c = 4 * k + g;
+    r[k] = (i < b && c <= i) ? D[c * lda + i] : 0.0;
   }
-  for (int c = cg; c < b; c += 4)
-    if (i < b && i >= c) D[c * lda + i] = a[i][c];
-  // row-major copy (row j of L11 contiguous) and reciprocal diagonal for
-  // the panel solve
-  if (i < b)
-    for (int c = cg; c < CB; c += 4) scratch[i * CB + c] = (c <= i && c < b) ? a[i][c] : 0.0;
-  if (cg == 0) scratch[CB * CB + i] = i < b ? 1.0 / a[i][i] : 0.0;
+  if (t == 0) bad = 0;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < CB; ++j) {
+    if (j >= b) break;  // uniform
+    double *cj = col[j & 1];
+    if (g == (j & 3)) {  // the wave that owns column j
+      const double piv = readlane_f64(r[j >> 2], j);
+      if (piv > 0.0) {
+        const double d = sqrt(piv);
+        const double l = i > j ? r[j >> 2] / d : (i == j ? d : 0.0);
+        r[j >> 2] = l;
+        cj[i] = i > j ? l : 0.0;
+        if (i == j) scratch[CB * CB + j] = 1.0 / d;  // reciprocal diagonal for the panel solve
+      } else if (i == 0) {
+        bad = 1;
+        *info = static_cast<int32_t>(k0 + j + 1);
+      }
+    }
+    __syncthreads();
+    if (bad) return;  // uniform: every thread reads the same flag after the barrier
+    const double li = cj[i];
+#pragma unroll
+    for (int k = 0; k < CB / 4; ++k) r[k] = fma(-li, cj[4 * k + g], r[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < CB / 4; ++k) {
+    const int c = 4 * k + g;
+    if (i < b && c <= i) D[c * lda + i] = r[k];
+    // row-major copy (row i of L11 contiguous) for the panel solve
+    if (i < b) scratch[i * CB + c] = c <= i ? r[k] : 0.0;
+  }
+  if (g == 0 && i >= b) scratch[CB * CB + i] = 0.0;
 }
 
 // Panel rows r >= k0 + 64: x solves x L11^T = a, left-looking: step j
