@@ -27,6 +27,14 @@
  *    by the caller; the paper sets mu = 0 without loss of generality,
  *    Section 2.1).  a_i = -inf and b_i = +inf are allowed.
  *  - A context is not thread safe; use one context per thread.
+ *  - Concurrent device linear algebra: rocBLAS / rocSOLVER factorizations
+ *    (and torch.linalg.cholesky) returned wrong results while this
+ *    library's estimator kernels ran beside them on other streams; the cause
+ *    has not been found (an audit of this library's device accesses found
+ *    no access outside its buffers).  Every rocBLAS call the library makes
+ *    itself runs with the device drained and to itself.  Callers should not
+ *    run their own device factorizations concurrently with mvn_prob,
+ *    mvt_prob or a server of this library: synchronize first.
  */
 #ifndef TLRQMC_H
 #define TLRQMC_H
@@ -191,10 +199,23 @@ void tlrqmc_factor_free(tlrqmc_factor *f);
  * frac(sqrt(p_{c+1})) (c = 0 the chi radius, c = 1..n the variables in
  * integration order) shifted by the SplitMix64 stream of `seed`
  * (Section 2.1, remark after the MVN algorithm; Section 3.4).
- *   precision 0: FP64 everywhere.
- *   precision 1: low-rank limit updates on BF16 MFMA with FP32
- *                accumulation and a hi/lo split correction; diagonal tiles,
- *                Phi, Phi^-1 and the log-space sums stay FP64.
+ *   precision 0: FP64 everywhere (arithmetic and every stored value).
+ *   precision 1: the precision form.
+ *     - Low-rank products (limit update U Z and projection V^T y, Section
+ *       3.4) on BF16 matrix cores with FP32 accumulation: each operand is
+ *       split into BF16 hi + lo and hi*hi + hi*lo + lo*hi is kept.
+ *     - The row products with the diagonal tiles (Section 2.1, Eq. 2) are
+ *       FP64 arithmetic.
+ *     - With a = -inf (one-sided limits) Phi, log Phi and Phi^-1 run in FP32
+ *       while the quantile's smaller side min(u, 1 - u) is at least 1e-36
+ *       (about 2e-7 relative error); below that the quantile is computed in
+ *       FP64 from log u.  Two-sided limits take the FP64 functions.
+ *     - y, the limit updates Delta and the rank-space images Z are stored
+ *       in FP32 between kernels (y is widened to FP64 for the row products).
+ *     - The complements, the running log P per sample and the per-shift
+ *       sums stay FP64.
+ *     Its error against the FP64 form is a few parts in 1e-6 of log P on
+ *     the benchmark workloads, well inside the QMC standard error.
  *   logp_out  : optional host array of n_shifts * n_samples doubles that
  *               receives log P of every sample (shift-major).
  *   profile   : nonzero records HIP events around every kernel launch and

@@ -1,17 +1,21 @@
 """Request server on the GPU: continuous batching and footprint admission.
 
-Checks that a served result equals the single-request path on the factor
-the library builds for the same request (tlr_factor + mvn_prob / mvt_prob),
-that it is the same bit for bit alone and in a mix of requests that run
-concurrently, that admission defers a request until memory is returned, and
-that requests that cannot fit or are invalid are refused.
+Checks that served results match the oracle run on the factor the server
+built (its checksum ties the rebuilt factor to the served one), that a
+served result equals the single-request path on the same factor
+(tlr_factor + mvn_prob / mvt_prob), that it is the same bit for bit alone
+and in a mix of requests that run concurrently, that admission defers a
+request until memory is returned, and that requests that cannot fit or are
+invalid are refused.
 """
 
+import math
 import time
 
 import numpy as np
 import pytest
 
+import oracle
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -61,6 +65,51 @@ def same(x, y):
 MIX = [req(64, 0.1, 0.0, 1, 1, N=120000), req(48, 0.3, 7.0, 1, 2), req(32, 0.05, 5.0, 0, 3),
        req(40, 0.2, 0.0, 0, 4, reorder=True), req(32, 0.1, 10.0, 1, 5, two_sided=True),
        req(64, 0.1, 0.0, 1, 6, N=3000), req(24, 0.3, 0.0, 1, 7, m=100)]
+
+
+def _oracle_of_served(ctx, r, served):
+    """Rebuild the request's factor (as the server does), check that it is the
+    served one, and run the oracle on its export with the request's lattice."""
+    n = len(r["a"])
+    perm = T.block_reorder(r["cov"], r["a"], r["b"], r["m"]) if r["reorder"] else None
+    F = T.Factor.build(ctx, r["cov"], n, r["m"], r["tol"], 0, perm=perm)
+    try:
+        assert F.stats()["checksum"] == served["info"]["factor_checksum"]
+        p, diag, rk, U, V = F.export()
+    finally:
+        F.free()
+    ref, _ = oracle.probability((diag, rk, U, V), r["a"][p], r["b"][p], r["nu"], r["N"], r["M"], r["seed"])
+    return ref
+
+
+# Served requests against the oracle: normal FP64 with block reordering,
+# Student-t in the precision form, and a two-sided Student-t (FP64), mixed in
+# one burst so that their slots share the batched launches.
+ORACLE_MIX = [req(32, 0.1, 0.0, 0, 21, N=2000, M=8, reorder=True),
+              req(28, 0.3, 7.0, 1, 22, N=2000, M=8),
+              req(24, 0.2, 5.0, 0, 23, N=2000, M=8, two_sided=True)]
+
+
+def test_served_results_match_the_oracle(ctx):
+    S = T.Server(ctx, 4 << 30)
+    try:
+        tickets = [submit(S, r) for r in ORACLE_MIX]
+        got = [S.result(t, timeout_s=120) for t in tickets]
+    finally:
+        S.close()
+    for r, g in zip(ORACLE_MIX, got):
+        ref = _oracle_of_served(ctx, r, g)
+        if r["precision"] == 0:
+            # FP64 bar: every shift's log-mean and the estimate to 1e-10 relative
+            for x, y in zip(g["log_p_shift"], ref["log_p_shift"]):
+                assert T.log_relative_gap(x, y) <= 1e-10
+            assert T.log_relative_gap(g["log_p"], ref["log_p"]) <= 1e-10
+            assert abs(g["rel_err"] - ref["rel_err"]) <= 1e-8 * ref["rel_err"]
+        else:
+            # precision form: |P - P_oracle| <= SE_oracle, in log space (P may
+            # be below the double range)
+            assert abs(math.expm1(g["log_p"] - ref["log_p"])) <= ref["rel_err"]
+            assert 0.5 * ref["rel_err"] <= g["rel_err"] <= 2.0 * ref["rel_err"]
 
 
 def test_server_matches_single_request_path(ctx):
@@ -145,20 +194,24 @@ def test_server_refuses_what_cannot_fit_and_invalid_requests(ctx):
 
 
 def test_server_stream_of_mixed_requests(ctx):
-    """A slice of the serving workload: mixed n, MVN/MVT, submitted as a burst."""
+    """A slice of the serving workload at its own sizes (N = 10,000 x 10 per
+    request): mixed n, MVN/MVT, submitted as a burst; every served result
+    equals the single-request path on the same factor."""
     reqs = synth.serving_stream(count=8)
     S = T.Server(ctx, 32 << 30)
     try:
-        tickets = [S.submit({"xy": q["xy"], "beta": q["beta"]}, q["a"], q["b"], 2000, q["M"], q["seed_shift"],
+        tickets = [S.submit({"xy": q["xy"], "beta": q["beta"]}, q["a"], q["b"], q["N"], q["M"], q["seed_shift"],
                             nu=q["nu"], m=q["m"], tol=1e-5, precision=1) for q in reqs]
         out = [S.result(t, timeout_s=120) for t in tickets]
     finally:
         S.close()
-    for q, o in zip(reqs[:3], out[:3]):
-        r = dict(cov={"xy": q["xy"], "beta": q["beta"]}, a=q["a"], b=q["b"], N=2000, M=q["M"], seed=q["seed_shift"],
+    assert len({q["n"] for q in reqs}) >= 2 and any(q["nu"] > 0 for q in reqs) and any(q["nu"] == 0 for q in reqs)
+    for q, o in zip(reqs, out):
+        r = dict(cov={"xy": q["xy"], "beta": q["beta"]}, a=q["a"], b=q["b"], N=q["N"], M=q["M"], seed=q["seed_shift"],
                  nu=q["nu"], m=q["m"], tol=1e-5, reorder=False, precision=1)
         ref = direct(ctx, r)
         assert T.log_relative_gap(o["log_p"], ref["log_p"]) <= 1e-13
+        np.testing.assert_allclose(o["log_p_shift"], ref["log_p_shift"], rtol=1e-13, atol=0)
     assert all(np.isfinite(o["log_p"]) for o in out)
 
 
