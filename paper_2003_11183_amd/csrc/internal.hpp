@@ -274,6 +274,8 @@ struct MfmaLrParams {
 
 int lr_mfma_rt(int rows);
 int64_t lr_mfma_rows(int rows);
+// Work-groups of one launch of lr_mfma over count samples and rows rows.
+int64_t lr_mfma_blocks(int64_t count, int rows);
 void launch_lr_mfma(hipStream_t s, const MfmaLrParams &p);
 void launch_init(hipStream_t s, const InitParams &p);
 void launch_sweep(hipStream_t s, const SweepParams &p, bool two_sided, bool scaled, bool prec);

@@ -5,7 +5,8 @@
 // kernel template:
 //   limit update : Delta_i = U_row(i) Z_row(i)     (m_i x K_row) (K_row x S)
 //   projection   : Z(:, j) = V_panel(j)^T Y_j      (K_col x m_j) (m_j x S)
-// Operands are split x = hi + lo into two BF16 numbers and multiplied as
+// Operands are split x = hi + lo into two BF16 numbers (each rounded to
+// nearest even) and multiplied as
 // hi*hi + hi*lo + lo*hi (the lo*lo term, below 2^-16 relative, is dropped)
 // with FP32 accumulation in v_mfma_f32_16x16x32_bf16.  The factor's U and V
 // are split once when the factor is built; Z (FP32) and Y (FP64) are split
@@ -27,16 +28,25 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-// Round-to-nearest-even float -> bf16 bits (finite input).
-__device__ __forceinline__ unsigned short bf16_bits(float x) {
-  unsigned u = __float_as_uint(x);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return static_cast<unsigned short>(u >> 16);
-}
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ void split2(float x, unsigned short &hi, unsigned short &lo) {
-  hi = bf16_bits(x);
-  lo = bf16_bits(x - __uint_as_float(static_cast<unsigned>(hi) << 16));
+// Split of eight values x = hi + lo into BF16 pairs, rounded to nearest even
+// (v_cvt_pk_bf16_f32 two at a time); lo is the rounding error of hi, itself
+// rounded, so hi + lo carries about 16 significant bits.
+template <class TB>
+__device__ __forceinline__ void split8(const TB (&v)[8], u16x8 &h, u16x8 &lo) {
+  unsigned hw[4], lw[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const f32x2 x = {static_cast<float>(v[2 * e]), static_cast<float>(v[2 * e + 1])};
+    const bf16x2 hb = __builtin_convertvector(x, bf16x2);
+    const bf16x2 lb = __builtin_convertvector(x - __builtin_convertvector(hb, f32x2), bf16x2);
+    hw[e] = __builtin_bit_cast(unsigned, hb);
+    lw[e] = __builtin_bit_cast(unsigned, lb);
+  }
+  h = __builtin_bit_cast(u16x8, hw);
+  lo = __builtin_bit_cast(u16x8, lw);
 }
 
 __device__ __forceinline__ f32x4 mfma3(u16x8 ah, u16x8 al, u16x8 bh, u16x8 bl, f32x4 c) {
@@ -50,51 +60,58 @@ __device__ __forceinline__ f32x4 mfma3(u16x8 ah, u16x8 al, u16x8 bh, u16x8 bl, f
 
 }  // namespace
 
-// C(row, s) = sum_k A(row, k) B(k, s).  Block: 64 samples and 64 RT rows
-// (four waves of RT row tiles of 16).  B is staged per 32-deep k step in
-// LDS, already split and in B-operand layout, double-buffered; the global
-// loads of step k + 64 are issued before the matrix products of step k, so
-// two steps of products cover their latency.
-// A (row-major, padded) is read straight from global memory (it is small
-// and shared by every sample block, so it stays in L2).
+// C(row, s) = sum_k A(row, k) B(k, s).  Block: 16 NT samples and 64 RT
+// rows (four waves of RT row tiles of 16; each wave covers all NT sample
+// tiles).  B is staged per 32-deep k step in LDS, already split and in
+// B-operand layout, double-buffered (wave w stages sample tiles w, w + 4,
+// ...); the global loads of step k + 64 are issued before the matrix
+// products of step k, so two steps of products cover their latency.  A
+// (row-major, padded) is read straight from global memory one step ahead
+// (it is small and shared by every sample block, so it stays in L2): a
+// wider sample block divides its reads by NT / 4.
 //
 // The grid is one-dimensional.  Work-groups are dealt to the eight XCDs
 // round robin, and each XCD has its own L2, so the linear id is remapped
 // such that every XCD receives a contiguous range of (sample block, row
 // block) pairs, row block fastest: the row blocks that share one sample
 // block's B run back to back on one XCD and re-read B from its L2.
-template <int RT, bool BD, bool MAP>
+template <int RT, int NT, bool BD, bool MAP>
 __device__ __forceinline__ void lr_mfma_body(const MfmaLrParams &p, unsigned bid, unsigned total) {
-  __shared__ u16x8 Bs[2][2][4][64];  // [buffer][hi, lo][sample tile][lane]
+  static_assert(NT % 4 == 0, "four waves stage the sample tiles");
+  constexpr int NS = NT / 4;  // sample tiles staged per wave
+  __shared__ u16x8 Bs[2][2][NT][64];  // [buffer][hi, lo][sample tile][lane]
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int nrb = (p.rows + 64 * RT - 1) / (64 * RT);
   const unsigned q = total / 8, rm = total % 8;
   const unsigned xcd = bid % 8, idx = bid / 8;
   const unsigned logical = xcd * q + min(xcd, rm) + idx;
   const unsigned rb = logical % static_cast<unsigned>(nrb), sb = logical / static_cast<unsigned>(nrb);
-  const int64_t s0 = static_cast<int64_t>(sb) * 64;
+  const int64_t s0 = static_cast<int64_t>(sb) * (16 * NT);
   const int r0 = static_cast<int>(rb) * 64 * RT + w * 16 * RT;
-  f32x4 acc[RT][4];
+  f32x4 acc[RT][NT];
 #pragma unroll
   for (int i = 0; i < RT; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  // staging role of this thread: sample tile w, B lane l
-  const int64_t ss = s0 + 16 * w + (l & 15);
-  const bool sok = ss < p.count;
+    for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // staging role of this thread: sample tiles w + 4 u (u < NS), B lane l
   const int kq = 8 * (l >> 4);
   using TB = typename std::conditional<BD, double, float>::type;
   const TB *B = BD ? reinterpret_cast<const TB *>(p.Bd) : reinterpret_cast<const TB *>(p.Bf);
   // Branch-free: a lane past the samples or a k past K reads element 0
   // (always valid) and keeps zero, so the loads are never predicated away.
   const auto Bg = dev::as_global(B);
-  auto load_b = [&](int kk, TB (&v)[8]) {
+  auto load_b = [&](int kk, TB (&v)[NS][8]) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int k = kk + kq + e;
-      const bool ok = sok && k < p.K;
-      const TB x = Bg[ok ? static_cast<int64_t>(k) * p.ld + ss : 0];
-      v[e] = ok ? x : TB(0);
+    for (int u = 0; u < NS; ++u) {
+      const int64_t ss = s0 + 16 * (w + 4 * u) + (l & 15);
+      const bool sok = ss < p.count;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = kk + kq + e;
+        const bool ok = sok && k < p.K;
+        const TB x = Bg[ok ? static_cast<int64_t>(k) * p.ld + ss : 0];
+        v[u][e] = ok ? x : TB(0);
+      }
     }
   };
   // A operand of one 32-deep step (this wave's row tiles), from global memory.
@@ -109,28 +126,26 @@ __device__ __forceinline__ void lr_mfma_body(const MfmaLrParams &p, unsigned bid
   // One 32-deep step: stage the B registers of this step into LDS buffer
   // buf, refill them with the step two ahead, fetch the next step's A
   // operand, multiply with this step's A.
-  auto step = [&](int kk, TB (&v)[8], int buf, u16x8 (&ah)[RT], u16x8 (&al)[RT], u16x8 (&nh)[RT],
+  auto step = [&](int kk, TB (&v)[NS][8], int buf, u16x8 (&ah)[RT], u16x8 (&al)[RT], u16x8 (&nh)[RT],
                   u16x8 (&nl)[RT]) {
-    u16x8 h, lo;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      unsigned short a, b;
-      split2(static_cast<float>(v[e]), a, b);
-      h[e] = a;
-      lo[e] = b;
+    for (int u = 0; u < NS; ++u) {
+      u16x8 h, lo;
+      split8(v[u], h, lo);
+      Bs[buf][0][w + 4 * u][l] = h;
+      Bs[buf][1][w + 4 * u][l] = lo;
     }
-    Bs[buf][0][w][l] = h;
-    Bs[buf][1][w][l] = lo;
     __syncthreads();
     if (kk + 64 < p.KP) load_b(kk + 64, v);
     if (kk + 32 < p.KP) load_a(kk + 32, nh, nl);
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
+    for (int t = 0; t < NT; ++t) {
+      const u16x8 bh = Bs[buf][0][t][l], bl = Bs[buf][1][t][l];
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        acc[rt][t] = mfma3(ah[rt], al[rt], Bs[buf][0][t][l], Bs[buf][1][t][l], acc[rt][t]);
+      for (int rt = 0; rt < RT; ++rt) acc[rt][t] = mfma3(ah[rt], al[rt], bh, bl, acc[rt][t]);
+    }
   };
-  TB va[8], vb[8];
+  TB va[NS][8], vb[NS][8];
   u16x8 a0h[RT], a0l[RT], a1h[RT], a1l[RT];
   load_b(0, va);
   if (32 < p.KP) load_b(32, vb);
@@ -147,27 +162,27 @@ __device__ __forceinline__ void lr_mfma_body(const MfmaLrParams &p, unsigned bid
       if (row >= p.rows) continue;
       float *o = p.Out + static_cast<int64_t>(MAP ? p.map[row] : row) * p.ld;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < NT; ++t) {
         const int64_t s = s0 + 16 * t + (l & 15);
         if (s < p.count) o[s] = acc[rt][t][i];
       }
     }
 }
 
-template <int RT, bool BD, bool MAP>
+template <int RT, int NT, bool BD, bool MAP>
 __global__ __launch_bounds__(256) void k_lr_mfma(MfmaLrParams p) {
-  lr_mfma_body<RT, BD, MAP>(p, blockIdx.x, gridDim.x);
+  lr_mfma_body<RT, NT, BD, MAP>(p, blockIdx.x, gridDim.x);
 }
 
 // Batched: slot = blockIdx.y; gridDim.x is a multiple of 8, so blockIdx.x
 // mod 8 is still the XCD of the work-group.
-template <int RT, bool BD, bool MAP>
+template <int RT, int NT, bool BD, bool MAP>
 __global__ __launch_bounds__(256) void k_lr_mfma_batch(const MfmaLrParams *ps) {
   const MfmaLrParams p = dev::load_uniform(ps + blockIdx.y);
-  const unsigned total =
-      static_cast<unsigned>((p.count + 63) / 64) * static_cast<unsigned>((p.rows + 64 * RT - 1) / (64 * RT));
+  const unsigned total = static_cast<unsigned>((p.count + 16 * NT - 1) / (16 * NT)) *
+                         static_cast<unsigned>((p.rows + 64 * RT - 1) / (64 * RT));
   if (blockIdx.x >= total) return;
-  lr_mfma_body<RT, BD, MAP>(p, blockIdx.x, total);
+  lr_mfma_body<RT, NT, BD, MAP>(p, blockIdx.x, total);
 }
 
 // Row tiles of 16 per wave: 1 or 2 for short operands, else 4 unless 2
@@ -182,25 +197,28 @@ int64_t lr_mfma_rows(int rows) { return round_up(rows > 0 ? rows : 1, 64 * lr_mf
 
 namespace {
 
+// Sample tiles of 16 per work-group.
+constexpr int kLrNT = 4;
+
 template <int RT>
 void launch_rt(hipStream_t s, const MfmaLrParams &p, dim3 grid) {
   if (p.Bd) {
-    if (p.map) hipLaunchKernelGGL((k_lr_mfma<RT, true, true>), grid, dim3(256), 0, s, p);
-    else hipLaunchKernelGGL((k_lr_mfma<RT, true, false>), grid, dim3(256), 0, s, p);
+    if (p.map) hipLaunchKernelGGL((k_lr_mfma<RT, kLrNT, true, true>), grid, dim3(256), 0, s, p);
+    else hipLaunchKernelGGL((k_lr_mfma<RT, kLrNT, true, false>), grid, dim3(256), 0, s, p);
   } else {
-    if (p.map) hipLaunchKernelGGL((k_lr_mfma<RT, false, true>), grid, dim3(256), 0, s, p);
-    else hipLaunchKernelGGL((k_lr_mfma<RT, false, false>), grid, dim3(256), 0, s, p);
+    if (p.map) hipLaunchKernelGGL((k_lr_mfma<RT, kLrNT, false, true>), grid, dim3(256), 0, s, p);
+    else hipLaunchKernelGGL((k_lr_mfma<RT, kLrNT, false, false>), grid, dim3(256), 0, s, p);
   }
 }
 
 template <int RT>
 void launch_batch_rt(hipStream_t s, const MfmaLrParams *d, dim3 grid, bool bd, bool map) {
   if (bd) {
-    if (map) hipLaunchKernelGGL((k_lr_mfma_batch<RT, true, true>), grid, dim3(256), 0, s, d);
-    else hipLaunchKernelGGL((k_lr_mfma_batch<RT, true, false>), grid, dim3(256), 0, s, d);
+    if (map) hipLaunchKernelGGL((k_lr_mfma_batch<RT, kLrNT, true, true>), grid, dim3(256), 0, s, d);
+    else hipLaunchKernelGGL((k_lr_mfma_batch<RT, kLrNT, true, false>), grid, dim3(256), 0, s, d);
   } else {
-    if (map) hipLaunchKernelGGL((k_lr_mfma_batch<RT, false, true>), grid, dim3(256), 0, s, d);
-    else hipLaunchKernelGGL((k_lr_mfma_batch<RT, false, false>), grid, dim3(256), 0, s, d);
+    if (map) hipLaunchKernelGGL((k_lr_mfma_batch<RT, kLrNT, false, true>), grid, dim3(256), 0, s, d);
+    else hipLaunchKernelGGL((k_lr_mfma_batch<RT, kLrNT, false, false>), grid, dim3(256), 0, s, d);
   }
 }
 
@@ -208,7 +226,7 @@ void launch_batch_rt(hipStream_t s, const MfmaLrParams *d, dim3 grid, bool bd, b
 
 void launch_lr_mfma(hipStream_t s, const MfmaLrParams &p) {
   const int rt = lr_mfma_rt(p.rows);
-  const int64_t nsb = (p.count + 63) / 64;
+  const int64_t nsb = (p.count + 16 * kLrNT - 1) / (16 * kLrNT);
   const int nrb = (p.rows + 64 * rt - 1) / (64 * rt);
   const dim3 grid(static_cast<unsigned>(nsb * nrb));
   if (rt == 1) launch_rt<1>(s, p, grid);
@@ -217,13 +235,19 @@ void launch_lr_mfma(hipStream_t s, const MfmaLrParams &p) {
 }
 
 // Every descriptor of one batched launch must have lr_mfma_rt(rows) == rt
-// and the same B type and map use; max_blocks bounds their block counts.
+// and the same B type and map use; max_blocks bounds their block counts
+// (lr_mfma_blocks).
 void launch_lr_mfma_batch(hipStream_t s, const MfmaLrParams *d, int n, int rt, bool fp64_b, bool map,
                           int64_t max_blocks) {
   const dim3 grid(static_cast<unsigned>(round_up(max_blocks, 8)), static_cast<unsigned>(n));
   if (rt == 1) launch_batch_rt<1>(s, d, grid, fp64_b, map);
   else if (rt == 2) launch_batch_rt<2>(s, d, grid, fp64_b, map);
   else launch_batch_rt<4>(s, d, grid, fp64_b, map);
+}
+
+int64_t lr_mfma_blocks(int64_t count, int rows) {
+  const int rt = lr_mfma_rt(rows);
+  return (count + 16 * kLrNT - 1) / (16 * kLrNT) * ((rows + 64 * rt - 1) / (64 * rt));
 }
 
 }  // namespace tlrqmc

@@ -530,7 +530,7 @@ int tlrqmc_server::step(StepBatch &B, int cur) {
         B.lr[0][rt_index(rt)].push_back(MfmaLrParams{s.cnt, ld, f->tm[j], static_cast<int>(f->krow[j]), f->kp_row[j], u,
                                                      u + f->ubf_size[j], s.ZF + f->zoffp[j] * ld, nullptr, nullptr,
                                                      s.DlF});
-        const int64_t blocks = (s.cnt + 63) / 64 * ((f->tm[j] + 64 * rt - 1) / (64 * rt));
+        const int64_t blocks = lr_mfma_blocks(s.cnt, f->tm[j]);
         B.lr_max[0][rt_index(rt)] = std::max(B.lr_max[0][rt_index(rt)], blocks);
       } else {
         B.f64[0].push_back(LrParams{s.cnt, ld, f->tm[j], static_cast<int>(f->krow[j]), f->urow_ld[j],
@@ -556,7 +556,7 @@ int tlrqmc_server::step(StepBatch &B, int cur) {
         B.lr[1][rt_index(rt)].push_back(MfmaLrParams{s.cnt, ld, rows, f->tm[j], f->vbf_mp[j], vv, vv + f->vbf_size[j],
                                                      static_cast<const float *>(s.Y), nullptr,
                                                      f->d_zmapp + f->zmap_off[j], s.ZF});
-        const int64_t blocks = (s.cnt + 63) / 64 * ((rows + 64 * rt - 1) / (64 * rt));
+        const int64_t blocks = lr_mfma_blocks(s.cnt, rows);
         B.lr_max[1][rt_index(rt)] = std::max(B.lr_max[1][rt_index(rt)], blocks);
       } else {
         B.f64[1].push_back(LrParams{s.cnt, ld, static_cast<int>(f->kcol[j]), f->tm[j], f->vpan_ld[j],
