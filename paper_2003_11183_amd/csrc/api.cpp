@@ -81,6 +81,7 @@ namespace {
 constexpr int64_t kMultiStreamSamples = 131072;
 constexpr int kWorkerStreams = 2;
 constexpr int64_t kScratchBudget = int64_t{64} << 30;
+constexpr int64_t kMaxChunk = int64_t{1} << 22;
 
 // HIP events around launches (on the launch's own stream), summed per
 // kernel kind.
@@ -220,7 +221,9 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
     const int64_t budget = kScratchBudget / nstream;
     chunk = std::max<int64_t>(256, std::min<int64_t>(budget / per_sample, (count + nstream - 1) / nstream));
   }
-  chunk = round_up(std::min(chunk, count), 256);
+  // at most 2^22 samples per chunk: the low-rank kernels address 32 rows of
+  // a chunk buffer with 32-bit byte offsets
+  chunk = round_up(std::min({chunk, count, kMaxChunk}), 256);
   const int64_t ld = chunk;
   SharedDevice dev;  // no library factorization runs beside these kernels
   Scratch sc(ctx);

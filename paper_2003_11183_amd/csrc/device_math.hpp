@@ -323,15 +323,16 @@ __device__ __forceinline__ float horner32(const float (&c)[N], float s) {
   return acc;
 }
 
-// erfcx(z) / 2 in FP32 for z >= 0: the rational-map polynomial up to
-// z = 8, the asymptotic series 1/(z sqrt(pi)) (1 - v + 3v^2 - 15v^3 +
-// 105v^4 - 945v^5), v = 1/(2z^2), beyond (error below 3e-9 there).
-__device__ __forceinline__ float half_erfcx32(float z) {
-  if (z <= kErfcx32Zmax) {
-    const float t = (z - kErfcx32K) * __builtin_amdgcn_rcpf(z + kErfcx32K);
-    const float g = horner32(kErfcx32, (t - kErfcx32C) * kErfcx32H);
-    return g * (1.0f - t) * 0.25f;
-  }
+// erfcx(z) / 2 in FP32 for 0 <= z <= 8: the rational-map polynomial.
+__device__ __forceinline__ float half_erfcx32_poly(float z) {
+  const float t = (z - kErfcx32K) * __builtin_amdgcn_rcpf(z + kErfcx32K);
+  const float g = horner32(kErfcx32, (t - kErfcx32C) * kErfcx32H);
+  return g * (1.0f - t) * 0.25f;
+}
+
+// erfcx(z) / 2 in FP32 for z > 8: the asymptotic series 1/(z sqrt(pi)) (1 -
+// v + 3v^2 - 15v^3 + 105v^4 - 945v^5), v = 1/(2z^2) (error below 3e-9).
+__device__ __forceinline__ float half_erfcx32_asym(float z) {
   const float r = __builtin_amdgcn_rcpf(z);
   const float v = 0.5f * r * r;
   const float sr = fmaf(fmaf(fmaf(fmaf(fmaf(-945.0f, v, 105.0f), v, -15.0f), v, 3.0f), v, -1.0f), v, 1.0f);
@@ -385,24 +386,41 @@ __device__ inline double sov_step_upper_fp32(double bh, double w, double &y) {
     return -INFINITY;
   }
   const double ab = fabs(bh);
-  const float ex = half_erfcx32(static_cast<float>(ab * M_SQRT1_2));
-  const double p2 = bh * bh;
-  const double a = 0.5 * p2;
-  const double al = isinf(bh) ? 0.0 : 0.5 * fma(bh, bh, -p2);  // bh^2 / 2 = a + al exactly
-  const double tt = fmin((a + al) * M_LOG2E, 200.0);
+  // erfcx(|bh|/sqrt2)/2.  Above zero and beyond z = 8 (bh > 11.3) the
+  // complement q is below 1e-29 and leaves e = 1 - q, u, c and log e
+  // unchanged in FP64, so any value of the right size will do there: the
+  // polynomial at z = 8.  Only the lower tail (bh < -11.3, where q itself is
+  // the probability) takes the asymptotic series, in a branch that is
+  // skipped unless a lane of the wave needs it.
+  const float zf = static_cast<float>(ab * M_SQRT1_2);
+  float ex = half_erfcx32_poly(fminf(zf, kErfcx32Zmax));
+  if (zf > kErfcx32Zmax && bh < 0.0) ex = half_erfcx32_asym(zf);
+  // q = Phi(-|bh|) = ex 2^-(tt) with tt = bh^2 log2(e) / 2 (its FP64 rounding
+  // moves q by about 1e-14 relative), split into integer and fraction
+  const double tt = fmin(bh * bh * (0.5 * M_LOG2E), 200.0);
   const double kf = floor(tt);
   const float q = __builtin_amdgcn_ldexpf(ex * __builtin_amdgcn_exp2f(-static_cast<float>(tt - kf)),
                                            -static_cast<int>(kf));
   const double qd = static_cast<double>(q);
-  const bool neg = bh < 0.0;
-  const double l_neg = static_cast<double>(__builtin_amdgcn_logf(ex) * kLn2f) - a - al;
-  const float v = q * __builtin_amdgcn_rcpf(2.0f - q);
-  const float v2 = v * v;
-  const float at = fmaf(fmaf(fmaf(fmaf(fmaf(fmaf(fmaf(1.0f / 15.0f, v2, 1.0f / 13.0f), v2, 1.0f / 11.0f), v2,
-                                            1.0f / 9.0f), v2, 1.0f / 7.0f), v2, 0.2f), v2, 1.0f / 3.0f), v2, 1.0f);
-  const double le = neg ? l_neg : static_cast<double>(-2.0f * v * at);
-  const double u = neg ? w * qd : fma(-w, qd, w);
-  const double c = neg ? 1.0 - u : fma(w, qd, 1.0 - w);
+  double le, u, c;
+  if (bh >= 0.0) {
+    // log1p(-q) = -2 atanh(q / (2 - q)), u = w (1 - q), c = (1 - w) + w q
+    const float v = q * __builtin_amdgcn_rcpf(2.0f - q);
+    const float v2 = v * v;
+    const float at = fmaf(fmaf(fmaf(fmaf(fmaf(fmaf(fmaf(1.0f / 15.0f, v2, 1.0f / 13.0f), v2, 1.0f / 11.0f), v2,
+                                              1.0f / 9.0f), v2, 1.0f / 7.0f), v2, 0.2f), v2, 1.0f / 3.0f), v2, 1.0f);
+    le = static_cast<double>(-2.0f * v * at);
+    u = fma(-w, qd, w);
+    c = fma(w, qd, 1.0 - w);
+  } else {
+    // log q = log(erfcx/2) - bh^2/2 with bh^2/2 = a + al split exactly
+    const double p2 = bh * bh;
+    const double a = 0.5 * p2;
+    const double al = 0.5 * fma(bh, bh, -p2);
+    le = static_cast<double>(__builtin_amdgcn_logf(ex) * kLn2f) - a - al;
+    u = w * qd;
+    c = 1.0 - u;
+  }
   const double pm = fmin(u, c);
   if (pm >= 1e-36) {
     const float pf = static_cast<float>(pm);

@@ -23,9 +23,13 @@ namespace tlrqmc {
 
 using namespace dev;
 
+// w = ((W >> 12) + 1/2) 2^-52 for the Q0.64 point W = k A + D (mod 2^64):
+// the 52 bits W >> 12 are the fraction of x = 1 + (W >> 12) 2^-52, and
+// x - (1 - 2^-53) = ((W >> 12) + 1/2) 2^-52 exactly (the difference has at
+// most 53 significant bits).
 __device__ __forceinline__ double lattice_point(uint64_t k, uint64_t A, uint64_t D) {
   const uint64_t W = k * A + D;
-  return (static_cast<double>(W >> 12) + 0.5) * 0x1p-52;
+  return __builtin_bit_cast(double, (W >> 12) | 0x3FF0000000000000ull) - (1.0 - 0x1p-53);
 }
 
 // ---------------------------------------------------------------- init ----
@@ -60,12 +64,18 @@ __global__ __launch_bounds__(256) void k_init_batch(const InitParams *ps) {
 // columns as well, entry [t*SB + i] = B(SB q + t + i, SB q + t) for i >= 1
 // (zero past the block) and entry [t*SB] = 1 / B(SB q + t, SB q + t).
 //
-// Within a row block the recursion is right looking: acc[i] holds the
-// partial row sum of row t + i; after y_t is known the column below the
-// diagonal is added and the window slides down by one, so every index into
-// acc is a compile-time constant and acc stays in registers.  (Unrolling the
-// sixteen rows instead, which would update only the triangle, measured half
-// as fast.)
+// Within a row block the recursion is right looking, in one of two forms
+// that sum every row's terms in the same (increasing column) order, so
+// they give identical results:
+//  - the one-sided precision form unrolls the sixteen rows: acc[r] holds
+//    the partial sum of row r of the block and, once y_t is known, column t
+//    below the diagonal is added to rows t+1..15 only (no register moves;
+//    a last, shorter block takes the rows it has by a wave-uniform branch);
+//  - the other forms, whose FP64 special functions need more registers,
+//    keep a sliding window: acc[i] holds the partial row sum of row t + i,
+//    the whole column is added and the window moves down by one.
+// Every index into acc is a compile-time constant, so acc stays in
+// registers.
 //
 // The per-lane operands of a row (shift word, low-rank update) are loaded
 // one row ahead and converted only when used, so that their memory latency
@@ -177,42 +187,65 @@ __device__ __forceinline__ void sweep_body(const SweepParams &p, int64_t si, dou
     const int rows = min(SB, p.mj - q * SB);
     const int r0 = q * SB;
     RowOperands<DT> nxt = row_operands(Ds, Dl, dls, r0);
-    {
-      // wave-uniform operands (limit, inverse diagonal, generator) of the
-      // next row are fetched one row ahead, and the column below the
-      // diagonal before the special functions that precede its use
-      double bn = bl[r0], an = TWO_SIDED ? al[r0] : 0.0, dn = blk[0];
-      uint64_t gn = Ag[r0];
+    // wave-uniform operands (limit, inverse diagonal, generator) of the next
+    // row are fetched one row ahead, and the column below the diagonal
+    // before the special functions that precede its use
+    double bn = bl[r0], an = TWO_SIDED ? al[r0] : 0.0, dn = blk[0];
+    uint64_t gn = Ag[r0];
+    // Row t of the block: prefetch row t + 1's operands, then y_t from the
+    // row's partial sum s (all its earlier terms).
+    // The unrolled form (TRI) reads only the entries below the diagonal
+    // (t is a compile-time constant there); the window reads the whole
+    // column, whose entries past the block are zero.
+    auto row_y = [&](int t, double s, double (&c)[SB], auto tri) -> double {
+      const int row = r0 + t;
+      const RowOperands<DT> cur = nxt;
+      const double bc = bn, ac = an, dinv = dn;
+      const uint64_t gc = gn;
+      const auto col = blk + t * SB;
+#pragma unroll
+      for (int i = 1; i < SB; ++i)
+        if (!decltype(tri)::value || t + i < SB) c[i] = col[i];
+      if (t + 1 < rows) {
+        nxt = row_operands(Ds, Dl, dls, row + 1);
+        bn = bl[row + 1];
+        if (TWO_SIDED) an = al[row + 1];
+        dn = col[SB];
+        gn = Ag[row + 1];
+      }
+      const double dl = static_cast<double>(cur.dl);
+      const double bt = R * bc - dl;
+      const double w = lattice_point(k, gc, cur.d);
+      double y;
+      if constexpr (TWO_SIDED) {
+        const double at = R * ac - dl;
+        lp += sov_step((at - s) * dinv, (bt - s) * dinv, w, y);
+      } else {
+        lp += PREC ? sov_step_upper_fp32((bt - s) * dinv, w, y) : sov_step_upper((bt - s) * dinv, w, y);
+      }
+      Y[row * ld] = static_cast<DT>(y);
+      return y;
+    };
+    if constexpr (PREC && !TWO_SIDED) {
+      // unrolled: column t below the diagonal goes to rows t+1..15 only
+#pragma unroll
+      for (int t = 0; t < SB; ++t) {
+        if (t < rows) {
+          double c[SB];
+          const double y = row_y(t, acc[t], c, std::true_type{});
+#pragma unroll
+          for (int i = 1; t + i < SB; ++i) acc[t + i] = fma(c[i], y, acc[t + i]);
+        }
+      }
+    } else {
+      // sliding window (fewer registers for the FP64 special functions):
+      // acc[i] holds the partial sum of row t + i; the window moves down by
+      // one row per step (entries past the block are zero in the layout)
       for (int t = 0; t < rows; ++t) {
-        const int row = r0 + t;
-        const RowOperands<DT> cur = nxt;
-        const double bc = bn, ac = an, dinv = dn;
-        const uint64_t gc = gn;
-        const auto col = blk + t * SB;
-        double c[SB - 1];
+        double c[SB];
+        const double y = row_y(t, acc[0], c, std::false_type{});
 #pragma unroll
-        for (int i = 1; i < SB; ++i) c[i - 1] = col[i];
-        if (t + 1 < rows) {
-          nxt = row_operands(Ds, Dl, dls, row + 1);
-          bn = bl[row + 1];
-          if (TWO_SIDED) an = al[row + 1];
-          dn = col[SB];
-          gn = Ag[row + 1];
-        }
-        const double dl = static_cast<double>(cur.dl);
-        const double bt = R * bc - dl;
-        const double w = lattice_point(k, gc, cur.d);
-        double y;
-        if constexpr (TWO_SIDED) {
-          const double at = R * ac - dl;
-          lp += sov_step((at - acc[0]) * dinv, (bt - acc[0]) * dinv, w, y);
-        } else {
-          lp += PREC ? sov_step_upper_fp32((bt - acc[0]) * dinv, w, y)
-                     : sov_step_upper((bt - acc[0]) * dinv, w, y);
-        }
-        Y[row * ld] = static_cast<DT>(y);
-#pragma unroll
-        for (int i = 1; i < SB; ++i) acc[i - 1] = fma(c[i - 1], y, acc[i]);
+        for (int i = 1; i < SB; ++i) acc[i - 1] = fma(c[i], y, acc[i]);
         acc[SB - 1] = 0.0;
       }
     }

@@ -85,7 +85,10 @@ __device__ __forceinline__ void lr_mfma_body(const MfmaLrParams &p, unsigned bid
   const unsigned q = total / 8, rm = total % 8;
   const unsigned xcd = bid % 8, idx = bid / 8;
   const unsigned logical = xcd * q + min(xcd, rm) + idx;
-  const unsigned rb = logical % static_cast<unsigned>(nrb), sb = logical / static_cast<unsigned>(nrb);
+  // wave-uniform by construction; readfirstlane lets the compiler keep them
+  // (and the buffer resources built from them) in scalar registers
+  const unsigned rb = __builtin_amdgcn_readfirstlane(logical % static_cast<unsigned>(nrb));
+  const unsigned sb = __builtin_amdgcn_readfirstlane(logical / static_cast<unsigned>(nrb));
   const int64_t s0 = static_cast<int64_t>(sb) * (16 * NT);
   const int r0 = static_cast<int>(rb) * 64 * RT + w * 16 * RT;
   f32x4 acc[RT][NT];
@@ -97,35 +100,52 @@ __device__ __forceinline__ void lr_mfma_body(const MfmaLrParams &p, unsigned bid
   const int kq = 8 * (l >> 4);
   using TB = typename std::conditional<BD, double, float>::type;
   const TB *B = BD ? reinterpret_cast<const TB *>(p.Bd) : reinterpret_cast<const TB *>(p.Bf);
-  // Branch-free: a lane past the samples or a k past K reads element 0
-  // (always valid) and keeps zero, so the loads are never predicated away.
-  const auto Bg = dev::as_global(B);
+  static_assert(16 * NT <= 256, "sample blocks must divide the leading dimension's multiple of 256");
+  // B through a buffer resource over the valid rows [kk, min(kk + 32, K))
+  // of each step: a k past K lies past the resource and reads zero in
+  // hardware, so no load is predicated or followed by a select (either
+  // would make the wave wait for the load at once).  A lane past the
+  // samples reads a column inside the leading dimension whose products land
+  // only in outputs that are not stored.  Offsets are 32-bit: 32 ld
+  // elements must stay below 2 GiB (the drivers bound ld).
+  const uint32_t lane_off = static_cast<uint32_t>(kq * p.ld + 16 * w + (l & 15)) * sizeof(TB);
+  const uint32_t row_bytes = static_cast<uint32_t>(p.ld * sizeof(TB));
   auto load_b = [&](int kk, TB (&v)[NS][8]) {
+    // rows of this step (none past K: every load reads zero); readfirstlane
+    // keeps the resource scalar (the clamp would otherwise go to the VALU)
+    const int bytes = __builtin_amdgcn_readfirstlane(static_cast<int>(max(0, min(32, p.K - kk)) * row_bytes));
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<TB *>(B) + static_cast<int64_t>(kk) * p.ld + s0, 0, bytes, 0x00020000);
 #pragma unroll
-    for (int u = 0; u < NS; ++u) {
-      const int64_t ss = s0 + 16 * (w + 4 * u) + (l & 15);
-      const bool sok = ss < p.count;
+    for (int u = 0; u < NS; ++u)
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const int k = kk + kq + e;
-        const bool ok = sok && k < p.K;
-        const TB x = Bg[ok ? static_cast<int64_t>(k) * p.ld + ss : 0];
-        v[u][e] = ok ? x : TB(0);
+        const int off = static_cast<int>(lane_off + (64 * u) * sizeof(TB) + e * row_bytes);
+        if constexpr (BD) {
+          v[u][e] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+        } else {
+          v[u][e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+        }
       }
-    }
   };
-  // A operand of one 32-deep step (this wave's row tiles), from global memory.
+  // A operand of one 32-deep step (this wave's row tiles), from global
+  // memory.  A step past the end reads the last step's columns again: they
+  // meet B rows of zero, so their products add exactly zero.
   auto load_a = [&](int kk, u16x8 (&ah)[RT], u16x8 (&al)[RT]) {
+    const int kc = min(kk, p.KP - 32);
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
-      const int64_t ro = static_cast<int64_t>(r0 + 16 * rt + (l & 15)) * p.KP + kk + kq;
+      const int64_t ro = static_cast<int64_t>(r0 + 16 * rt + (l & 15)) * p.KP + kc + kq;
       ah[rt] = *reinterpret_cast<const u16x8 *>(p.Ahi + ro);
       al[rt] = *reinterpret_cast<const u16x8 *>(p.Alo + ro);
     }
   };
   // One 32-deep step: stage the B registers of this step into LDS buffer
   // buf, refill them with the step two ahead, fetch the next step's A
-  // operand, multiply with this step's A.
+  // operand, multiply with this step's A.  The prefetches are issued
+  // unconditionally (past the end they read zeros or repeat the last
+  // columns): a conditional load would make the compiler wait for every
+  // load in flight where the paths join.
   auto step = [&](int kk, TB (&v)[NS][8], int buf, u16x8 (&ah)[RT], u16x8 (&al)[RT], u16x8 (&nh)[RT],
                   u16x8 (&nl)[RT]) {
 #pragma unroll
@@ -136,8 +156,13 @@ __device__ __forceinline__ void lr_mfma_body(const MfmaLrParams &p, unsigned bid
       Bs[buf][1][w + 4 * u][l] = lo;
     }
     __syncthreads();
-    if (kk + 64 < p.KP) load_b(kk + 64, v);
-    if (kk + 32 < p.KP) load_a(kk + 32, nh, nl);
+    // A of the next step before B of the step after it: loads complete in
+    // order of issue, so the wait for the A operand leaves B in flight
+    load_a(kk + 32, nh, nl);
+    load_b(kk + 64, v);
+    // keep the prefetches ahead of this step's products (the scheduler
+    // would otherwise sink them below, leaving them no time in flight)
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const u16x8 bh = Bs[buf][0][t][l], bl = Bs[buf][1][t][l];
@@ -148,12 +173,14 @@ __device__ __forceinline__ void lr_mfma_body(const MfmaLrParams &p, unsigned bid
   TB va[NS][8], vb[NS][8];
   u16x8 a0h[RT], a0l[RT], a1h[RT], a1l[RT];
   load_b(0, va);
-  if (32 < p.KP) load_b(32, vb);
+  load_b(32, vb);
   load_a(0, a0h, a0l);
-  for (int kk = 0; kk < p.KP; kk += 64) {
+  const int nsteps = p.KP / 32;
+  for (int kk = 0; kk + 64 <= 32 * nsteps; kk += 64) {
     step(kk, va, 0, a0h, a0l, a1h, a1l);
-    if (kk + 32 < p.KP) step(kk + 32, vb, 1, a1h, a1l, a0h, a0l);
+    step(kk + 32, vb, 1, a1h, a1l, a0h, a0l);
   }
+  if (nsteps & 1) step(32 * (nsteps - 1), va, 0, a0h, a0l, a1h, a1l);
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -185,20 +212,17 @@ __global__ __launch_bounds__(256) void k_lr_mfma_batch(const MfmaLrParams *ps) {
   lr_mfma_body<RT, NT, BD, MAP>(p, blockIdx.x, total);
 }
 
-// Row tiles of 16 per wave: 1 or 2 for short operands, else 4 unless 2
-// pads less.
-int lr_mfma_rt(int rows) {
-  if (rows <= 64) return 1;
-  if (rows <= 128) return 2;
-  return round_up(rows, 256) == round_up(rows, 128) ? 4 : 2;
-}
+// Row tiles of 16 per wave: one for operands of at most 64 rows, else two
+// (measured at n = 16,384 against four, with 64-, 128- and 256-sample
+// blocks: 128 samples and two row tiles were fastest for both products).
+int lr_mfma_rt(int rows) { return rows <= 64 ? 1 : 2; }
 
 int64_t lr_mfma_rows(int rows) { return round_up(rows > 0 ? rows : 1, 64 * lr_mfma_rt(rows)); }
 
 namespace {
 
-// Sample tiles of 16 per work-group.
-constexpr int kLrNT = 4;
+// Sample tiles of 16 per work-group (128 samples).
+constexpr int kLrNT = 8;
 
 template <int RT>
 void launch_rt(hipStream_t s, const MfmaLrParams &p, dim3 grid) {
@@ -230,8 +254,7 @@ void launch_lr_mfma(hipStream_t s, const MfmaLrParams &p) {
   const int nrb = (p.rows + 64 * rt - 1) / (64 * rt);
   const dim3 grid(static_cast<unsigned>(nsb * nrb));
   if (rt == 1) launch_rt<1>(s, p, grid);
-  else if (rt == 2) launch_rt<2>(s, p, grid);
-  else launch_rt<4>(s, p, grid);
+  else launch_rt<2>(s, p, grid);
 }
 
 // Every descriptor of one batched launch must have lr_mfma_rt(rows) == rt
@@ -241,8 +264,7 @@ void launch_lr_mfma_batch(hipStream_t s, const MfmaLrParams *d, int n, int rt, b
                           int64_t max_blocks) {
   const dim3 grid(static_cast<unsigned>(round_up(max_blocks, 8)), static_cast<unsigned>(n));
   if (rt == 1) launch_batch_rt<1>(s, d, grid, fp64_b, map);
-  else if (rt == 2) launch_batch_rt<2>(s, d, grid, fp64_b, map);
-  else launch_batch_rt<4>(s, d, grid, fp64_b, map);
+  else launch_batch_rt<2>(s, d, grid, fp64_b, map);
 }
 
 int64_t lr_mfma_blocks(int64_t count, int rows) {
