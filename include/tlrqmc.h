@@ -271,6 +271,27 @@ int mvn_prob(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, const dou
 int mvt_prob(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, const double *b,
              double nu, const tlrqmc_qmc_opts *opts, tlrqmc_result *out);
 
+/* mvn_prob (nu = 0) or mvt_prob (nu > 0) without allocating: for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  The result equals
+ * mvn_prob / mvt_prob on the same arguments bit for bit (the same kernels
+ * and per-sample arithmetic; samples are swept in chunks of a size that
+ * fits the scratch, one stream).
+ *   Scratch: a 256 MiB file-scope device array of the library, one per
+ *   device, held from module load to process end; its address is resolved
+ *   by tlrqmc_ctx_create.  Limits, shift table, per-sample log P (8 bytes
+ *   per sample) and the chunk buffers come from it.  A problem whose
+ *   per-call arrays and one chunk of 256 samples do not fit returns
+ *   TLRQMC_ENOMEM with the sizes in the message, before any device work.
+ *   Calls that overlap on one device race on the array: the caller
+ *   serializes them.  The array keeps the last call's contents.
+ *   The call creates no device objects (no streams, no events; opts.profile
+ *   is ignored and result.seconds is host wall time) and issues everything
+ *   on the context stream; it returns after that work has completed.
+ *   Arguments and errors otherwise as mvn_prob / mvt_prob (nu >= 0). */
+int tlrqmc_prob_noalloc(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, const double *b, double nu,
+                        const tlrqmc_qmc_opts *opts, tlrqmc_result *out);
+
 /* log P of samples k0 .. k0+count-1 (1-based) of shift `shift`, run through
  * the same kernels as mvn_prob / mvt_prob (nu = 0 selects MVN).  logp_out:
  * host, count entries. */

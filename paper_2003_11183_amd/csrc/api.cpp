@@ -6,6 +6,7 @@
 // of its y values, then one reduction per shift.  Student-t problems
 // (Section 2.2, Eq. 4) add a per-sample chi radius computed at chunk start.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -165,12 +166,31 @@ int fail_device(tlrqmc_ctx *ctx, size_t nworkers) {
   return TLRQMC_EDEVICE;
 }
 
-// Shared driver of mvn_prob, mvt_prob and tlrqmc_sample_logp.  Samples
-// g0 .. g0+count-1 of the flattened (shift, k) index space are swept; a
-// full estimate (reduce = true) needs g0 = 0 and count = N M.
+// A fixed device region handed out by a bump pointer (256-byte aligned
+// pieces); take() returns null once it is used up.
+struct FixedRegion {
+  char *p;
+  size_t left;
+  void *take(size_t bytes) {
+    const size_t need = static_cast<size_t>(round_up(static_cast<int64_t>(bytes ? bytes : 1), 256));
+    if (need > left) return nullptr;
+    void *q = p;
+    p += need;
+    left -= need;
+    return q;
+  }
+};
+
+// Shared driver of mvn_prob, mvt_prob, tlrqmc_sample_logp and
+// tlrqmc_prob_noalloc.  Samples g0 .. g0+count-1 of the flattened (shift,
+// k) index space are swept; a full estimate (reduce = true) needs g0 = 0 and
+// count = N M.  With fixed != null every device buffer comes from that
+// region instead of the allocator, the chunks are sized to fit it, and the
+// call runs on the context stream alone with no events (so it creates
+// nothing on the device); its seconds are host wall time.
 int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, const double *b,
                   double nu, const tlrqmc_qmc_opts *opts, int64_t g0, int64_t count,
-                  bool reduce, double *logp_host, tlrqmc_result *out) {
+                  bool reduce, double *logp_host, tlrqmc_result *out, FixedRegion *fixed = nullptr) {
   clear_error();
   if (!ctx || !f || !a || !b || !opts) return fail(TLRQMC_EINVAL, "null argument");
   if (f->ctx != ctx) return fail(TLRQMC_EINVAL, "factor belongs to another context");
@@ -215,9 +235,24 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
   const bool prec = opts->precision == 1;
   const int64_t mpad = round_up(f->m, 64);
   const int64_t per_sample = prec ? 4 * f->zp_tot + 8 * mpad + 16 : 8 * (f->k_tot + 2 * mpad + 2);
-  const int nstream = count >= kMultiStreamSamples ? kWorkerStreams : 1;
+  const int nstream = (!fixed && count >= kMultiStreamSamples) ? kWorkerStreams : 1;
   int64_t chunk = opts->chunk_samples;
-  if (chunk <= 0) {
+  if (fixed) {
+    // what is left of the region after the per-call arrays, in chunks of 256
+    const int64_t fixed_bytes = (two_sided ? round_up(8 * n, 256) : 0) + round_up(8 * n, 256) +
+                                round_up(8 * static_cast<int64_t>(M) * (n + 1), 256) + round_up(8 * count, 256) +
+                                (reduce ? round_up(8 * 3 * M, 256) : 0);
+    const int64_t room = static_cast<int64_t>(fixed->left) - fixed_bytes - 5 * 256;
+    const int64_t fit = room > 0 ? room / per_sample / 256 * 256 : 0;
+    if (fit < 256)
+      return fail(TLRQMC_ENOMEM,
+                  "the problem does not fit the %lld MiB no-allocation scratch (n = %lld, %lld samples: %lld bytes "
+                  "of per-call arrays plus %lld per sample, chunks of at least 256 samples)",
+                  static_cast<long long>(noalloc_scratch_bytes() >> 20), static_cast<long long>(n),
+                  static_cast<long long>(count), static_cast<long long>(fixed_bytes),
+                  static_cast<long long>(per_sample));
+    chunk = chunk > 0 ? std::min(chunk, fit) : fit;
+  } else if (chunk <= 0) {
     const int64_t budget = kScratchBudget / nstream;
     chunk = std::max<int64_t>(256, std::min<int64_t>(budget / per_sample, (count + nstream - 1) / nstream));
   }
@@ -227,11 +262,12 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
   const int64_t ld = chunk;
   SharedDevice dev;  // no library factorization runs beside these kernels
   Scratch sc(ctx);
-  double *d_a = two_sided ? sc.get<double>(n) : nullptr;
-  double *d_b = sc.get<double>(n);
-  uint64_t *d_D = sc.get<uint64_t>(static_cast<size_t>(M) * (n + 1));
-  double *d_logp = sc.get<double>(count);
-  double *d_part = reduce ? sc.get<double>(3 * M) : nullptr;
+  auto take = [&](size_t bytes) -> void * { return fixed ? fixed->take(bytes) : sc.get<char>(bytes); };
+  double *d_a = two_sided ? static_cast<double *>(take(8 * n)) : nullptr;
+  double *d_b = static_cast<double *>(take(8 * n));
+  uint64_t *d_D = static_cast<uint64_t *>(take(8 * static_cast<size_t>(M) * (n + 1)));
+  double *d_logp = static_cast<double *>(take(8 * count));
+  double *d_part = reduce ? static_cast<double *>(take(8 * 3 * M)) : nullptr;
   if (!d_b || !d_D || !d_logp || (two_sided && !d_a) || (reduce && !d_part))
     return fail(TLRQMC_ENOMEM, "device allocation failed");
   struct Lane {
@@ -245,13 +281,13 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
   for (int w = 0; w < nstream; ++w) {
     Lane &L = lanes[w];
     L.s = nstream > 1 ? ctx->workers[w] : ctx->stream;
-    L.Y = prec ? static_cast<void *>(sc.get<float>(static_cast<size_t>(mpad) * ld))
-               : static_cast<void *>(sc.get<double>(static_cast<size_t>(mpad) * ld));
-    L.Dl = (!prec && r > 1) ? sc.get<double>(static_cast<size_t>(mpad) * ld) : nullptr;
-    L.Z = (!prec && f->k_tot > 0) ? sc.get<double>(static_cast<size_t>(f->k_tot) * ld) : nullptr;
-    L.DlF = (prec && r > 1) ? sc.get<float>(static_cast<size_t>(mpad) * ld) : nullptr;
-    L.ZF = (prec && f->k_tot > 0) ? sc.get<float>(static_cast<size_t>(f->zp_tot) * ld) : nullptr;
-    L.R = nu > 0 ? sc.get<double>(chunk) : nullptr;
+    const size_t cols = static_cast<size_t>(ld);
+    L.Y = take((prec ? 4 : 8) * static_cast<size_t>(mpad) * cols);
+    L.Dl = (!prec && r > 1) ? static_cast<double *>(take(8 * static_cast<size_t>(mpad) * cols)) : nullptr;
+    L.Z = (!prec && f->k_tot > 0) ? static_cast<double *>(take(8 * static_cast<size_t>(f->k_tot) * cols)) : nullptr;
+    L.DlF = (prec && r > 1) ? static_cast<float *>(take(4 * static_cast<size_t>(mpad) * cols)) : nullptr;
+    L.ZF = (prec && f->k_tot > 0) ? static_cast<float *>(take(4 * static_cast<size_t>(f->zp_tot) * cols)) : nullptr;
+    L.R = nu > 0 ? static_cast<double *>(take(8 * cols)) : nullptr;
     if (!L.Y || (!prec && r > 1 && !L.Dl) || (!prec && f->k_tot > 0 && !L.Z) || (prec && r > 1 && !L.DlF) ||
         (prec && f->k_tot > 0 && !L.ZF) || (nu > 0 && !L.R))
       return fail(TLRQMC_ENOMEM, "device allocation failed (chunk of %lld samples)", static_cast<long long>(chunk));
@@ -264,11 +300,17 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
       hipMemcpyAsync(d_D, shifts.data(), shifts.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess)
     return fail(TLRQMC_EDEVICE, "copy of limits or shifts failed");
   Events evs;
-  hipEvent_t ev0 = evs.make(), ev1 = evs.make(), ev_in = evs.make();
-  if (!ev0 || !ev1 || !ev_in) return fail(TLRQMC_EDEVICE, "hipEventCreate failed");
-  Profiler prof(opts->profile != 0);
-  (void)hipEventRecord(ev0, st);
-  (void)hipEventRecord(ev_in, st);
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_in = nullptr;
+  if (!fixed) {
+    ev0 = evs.make();
+    ev1 = evs.make();
+    ev_in = evs.make();
+    if (!ev0 || !ev1 || !ev_in) return fail(TLRQMC_EDEVICE, "hipEventCreate failed");
+  }
+  const auto t_host0 = std::chrono::steady_clock::now();
+  Profiler prof(!fixed && opts->profile != 0);
+  if (ev0) (void)hipEventRecord(ev0, st);
+  if (ev_in) (void)hipEventRecord(ev_in, st);
   if (nstream > 1)
     for (auto &L : lanes) (void)hipStreamWaitEvent(L.s, ev_in, 0);
   int chunks = 0;
@@ -350,7 +392,7 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
     prof.end(st);
     if (!check_launch("reduce")) return fail_device(ctx, lanes.size());
   }
-  (void)hipEventRecord(ev1, st);
+  if (ev1) (void)hipEventRecord(ev1, st);
   {
     std::vector<double> part(reduce ? 3 * M : 0);
     if (reduce && hipMemcpyAsync(part.data(), d_part, part.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess)
@@ -359,12 +401,13 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
       return fail_device(ctx, lanes.size());
     if (hipStreamSynchronize(st) != hipSuccess) return fail_device(ctx, lanes.size());
     float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, ev0, ev1);
+    if (ev0) (void)hipEventElapsedTime(&ms, ev0, ev1);
+    else ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t_host0).count();
     if (out) {
       if (reduce) estimate_from_parts(part, M, N, out);
       out->seconds = ms * 1e-3;
       out->chunks = chunks;
-      prof.collect(out, ev0);
+      if (ev0) prof.collect(out, ev0);
     }
   }
   return TLRQMC_OK;
@@ -431,6 +474,9 @@ int tlrqmc_ctx_create(int device, void *hip_stream, const tlrqmc_allocator *allo
     return fail(TLRQMC_EDEVICE, "no HIP device available");
   if (device < 0 || device >= count) return fail(TLRQMC_EINVAL, "device %d out of range", device);
   if (hipSetDevice(device) != hipSuccess) return fail(TLRQMC_EDEVICE, "hipSetDevice(%d) failed", device);
+  // the no-allocation entry point's scratch array: its address on this
+  // device, resolved once per device with the device current
+  if (noalloc_resolve(device) != TLRQMC_OK) return TLRQMC_EDEVICE;
   auto c = new tlrqmc_ctx();
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
@@ -521,6 +567,18 @@ int mvt_prob(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, const dou
   if (!(nu > 0.0)) return fail(TLRQMC_EINVAL, "nu must be > 0");
   return run_estimator(ctx, f, a, b, nu, opts, 0, opts->n_samples * opts->n_shifts, true,
                        opts->logp_out, out);
+}
+
+int tlrqmc_prob_noalloc(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, const double *b, double nu,
+                        const tlrqmc_qmc_opts *opts, tlrqmc_result *out) {
+  if (!opts || !out) return fail(TLRQMC_EINVAL, "null opts or result");
+  if (!ctx) return fail(TLRQMC_EINVAL, "null context");
+  if (!(nu >= 0.0)) return fail(TLRQMC_EINVAL, "nu must be >= 0 (0 selects MVN)");
+  void *base = noalloc_scratch(ctx->device);
+  if (!base) return fail(TLRQMC_EDEVICE, "no-allocation scratch not resolved on device %d", ctx->device);
+  FixedRegion region{static_cast<char *>(base), static_cast<size_t>(noalloc_scratch_bytes())};
+  return run_estimator(ctx, f, a, b, nu, opts, 0, opts->n_samples * opts->n_shifts, true, opts->logp_out, out,
+                       &region);
 }
 
 int tlrqmc_sample_logp(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, const double *b,

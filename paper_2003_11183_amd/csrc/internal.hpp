@@ -209,6 +209,15 @@ int factor_from_device_dense(tlrqmc_ctx *ctx, int64_t n, const double *S, int64_
                              const double *b, const double *xy, int m, double tol, int max_rank, int order,
                              int32_t *perm_out, tlrqmc_factor **out);
 
+// ---- no-allocation scratch (noalloc.hip) ----
+// Size of the file-scope device array behind tlrqmc_prob_noalloc.
+int64_t noalloc_scratch_bytes();
+// Resolve (once per device, with the device made current) and keep the
+// array's device address; TLRQMC_EDEVICE with a message on failure.
+int noalloc_resolve(int device);
+// The array's address on `device`, or null if it was not resolved.
+void *noalloc_scratch(int device);
+
 // ---- host lattice (lattice.cpp) ----
 std::vector<uint64_t> richtmyer_generators(int64_t dim);
 std::vector<uint64_t> splitmix64_table(uint64_t seed, int64_t count);

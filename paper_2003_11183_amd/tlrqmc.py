@@ -115,6 +115,8 @@ SIGNATURES = {
     "mvn_prob": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(QmcOpts), C.POINTER(Result)]),
     "mvt_prob": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.POINTER(QmcOpts),
                            C.POINTER(Result)]),
+    "tlrqmc_prob_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                      C.POINTER(QmcOpts), C.POINTER(Result)]),
     "tlrqmc_sample_logp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                                      C.POINTER(QmcOpts), C.c_int32, C.c_int64, C.c_int64, C.c_void_p]),
     "tlrqmc_skewnormal_loglik": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.POINTER(SkewNormalParams),
@@ -381,6 +383,21 @@ def probability(ctx: Context, factor: Factor, a, b, N: int, M: int, seed: int, n
     if return_logp:
         out["logp"] = logp.reshape(int(M), int(N))
     return out
+
+
+def probability_noalloc(ctx: Context, factor: Factor, a, b, N: int, M: int, seed: int, nu: float = 0.0,
+                        precision: int = 0, chunk: int = 0) -> dict:
+    """tlrqmc_prob_noalloc: the estimate of probability() with every device
+    buffer taken from the library's fixed scratch array (no allocation)."""
+    a, b = _f64(a), _f64(b)
+    n = factor.stats()["n"]
+    if a.shape != (n,) or b.shape != (n,):
+        raise ValueError(f"a and b must have {n} entries")
+    o = _opts(N, M, seed, precision, None, False, chunk)
+    res = Result()
+    st = _check(lib().tlrqmc_prob_noalloc(ctx.handle, factor.handle, a.ctypes.data, b.ctypes.data, float(nu),
+                                          C.byref(o), C.byref(res)))
+    return _result(res, st)
 
 
 def mvn_prob(ctx, factor, a, b, N, M, seed, **kw):
