@@ -19,6 +19,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -29,26 +30,48 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "QMC sample·dims/sec at n=16384 (FP64 vs BF16-MFMA); p50/p99 latency per prob"
-PEAK_FP64_VALU = 78.6e12    # 256 CU x 2.4 GHz x 64 lanes x 2 flops (FMA)
+PEAK_FP64 = 78.6e12         # FP64 vector ALU and FP64 matrix cores alike: 256 CU x 2.4 GHz x 128 flop/clk
+PEAK_FP32 = 157.3e12        # FP32 vector (published; packed FP32 instructions are not used here)
 PEAK_BF16_MFMA = 2.5e15     # dense
-# FP64 operations per variable of the sweep beyond the row products (Phi, log,
-# Phi^-1, lattice point, bookkeeping).
-C_PHI = 150
+PEAK_HBM = 8.0e12           # bytes/s
+# kept for the tests of the per-kind pricing: the FP64 vector peak
+PEAK_FP64_VALU = PEAK_FP64
+
+# Vector-ALU operations per variable of the sweep beyond the row products
+# (the special functions, the lattice point, the limit and the quantile
+# bookkeeping), per form, from rocprofv3 instruction counters of the sweep
+# on the n = 16,384 workload (profiles/sweep_valu_ops_n16384.md):
+# flops counted as FMA = 2, ADD/MUL/transcendental = 1, per lane and row,
+# minus the FMAs of the in-block row products.  Reported only while the
+# kernel sources have the digest they were measured on.
+CPHI = {
+    1: {"f64": None, "f32": None, "digest": None},
+    0: {"f64": None, "f32": None, "digest": None},
+}
+
+
+def note(msg: str) -> None:
+    """Progress on stderr (stdout carries the one JSON line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--precision", type=int, default=-1, help="-1 = the workload's own form")
     ap.add_argument("--no-fp64-form", action="store_true", help="skip timing the FP64 form beside it")
+    ap.add_argument("--extra-configs", default="1,4",
+                    help="other workloads measured after the headline one (both forms), comma separated; '' = none")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=1536)
-    ap.add_argument("--serve", type=int, default=100, metavar="COUNT",
+    ap.add_argument("--cpu-samples-1t", type=int, default=128,
+                    help="lattice points of the single-thread oracle timing")
+    ap.add_argument("--serve", type=int, default=2000, metavar="COUNT",
                     help="requests of the mixed-dimension serving stream to replay (0 = skip)")
-    ap.add_argument("--serve-fp64", type=int, default=12, metavar="COUNT",
+    ap.add_argument("--serve-fp64", type=int, default=100, metavar="COUNT",
                     help="of those, how many also run one at a time through the plain FP64 path")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--no-reorder-study", action="store_true",
@@ -58,20 +81,67 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_work(kind: str, st: dict, n: int, m: int, precision: int) -> tuple[float, str, float]:
-    """Algorithmic work per sample of all launches of one kernel kind, its
-    bound and the peak of that bound: the precision form's low-rank products
-    run on BF16 matrix cores, the FP64 form's limit update on FP64 matrix
-    cores and its projection on the FP64 vector ALU (both 78.6 TFLOP/s)."""
+def tile_sizes(n: int, m: int) -> list[int]:
+    return [min(m, n - i * m) for i in range((n + m - 1) // m)]
+
+
+def sweep_row_flops(n: int, m: int, sb: int = 16) -> tuple[int, int]:
+    """Exact row-product flops per sample of the diagonal tiles (2 per
+    multiply-add): (rows of earlier 16-row blocks, on FP64 matrix cores;
+    rows inside a block, on the FP64 vector ALU)."""
+    mf = va = 0
+    for mi in tile_sizes(n, m):
+        inb = sum(min(sb, mi - q) * (min(sb, mi - q) - 1) for q in range(0, mi, sb))
+        va += inb
+        mf += mi * (mi - 1) - inb
+    return mf, va
+
+
+def cphi_of(precision: int):
+    e = CPHI.get(precision)
+    if e and e["digest"] == kernel_digest() and e["f64"] is not None:
+        return e
+    return None
+
+
+def kernel_work(kind: str, st: dict, n: int, m: int, precision: int) -> dict:
+    """Algorithmic work per sample of one kernel kind, split by the pipe it
+    runs on: fp64_mfma / bf16_mfma (flops as executed: three BF16 products
+    per low-rank product in the precision form), fp64_valu, fp32_valu
+    (flops), and the algorithmic HBM bytes."""
+    k_tot = st["k_tot"]
     if kind == "sweep":
-        tri = sum(min(m, n - i * m) * (min(m, n - i * m) - 1) for i in range((n + m - 1) // m))
-        return tri + C_PHI * n, "alu", PEAK_FP64_VALU
+        mf, va = sweep_row_flops(n, m)
+        cp = cphi_of(precision)
+        f64 = va + (cp["f64"] * n if cp else 0.0)
+        f32 = cp["f32"] * n if cp else 0.0
+        # low-rank update read and y written once per row (FP32 each in the
+        # precision form, FP64 in the FP64 form), log P read and written,
+        # the radius read
+        by = (8 if precision == 1 else 16) * n + 24 * ((n + m - 1) // m)
+        return {"fp64_mfma": float(mf), "fp64_valu": float(f64), "fp32_valu": float(f32), "bf16_mfma": 0.0,
+                "rows": float(mf + va), "cphi": cp, "bytes": float(by)}
     if kind in ("delta", "zproj"):
-        f = 2.0 * m * st["k_tot"]
+        f = 2.0 * m * k_tot
+        wb = 4 if precision == 1 else 8
+        by = wb * (k_tot + n) * 1.0  # input read once, output written once
         if precision == 1:
-            return 3 * f, "mfma", PEAK_BF16_MFMA
-        return f, ("mfma" if kind == "delta" else "alu"), PEAK_FP64_VALU
-    return float("nan"), "alu", PEAK_FP64_VALU
+            return {"bf16_mfma": 3 * f, "fp64_mfma": 0.0, "fp64_valu": 0.0, "fp32_valu": 0.0, "alg": f, "bytes": by}
+        if kind == "delta":
+            return {"fp64_mfma": f, "bf16_mfma": 0.0, "fp64_valu": 0.0, "fp32_valu": 0.0, "alg": f, "bytes": by}
+        return {"fp64_valu": f, "fp64_mfma": 0.0, "bf16_mfma": 0.0, "fp32_valu": 0.0, "alg": f, "bytes": by}
+    return {"fp64_valu": float("nan"), "fp64_mfma": 0.0, "bf16_mfma": 0.0, "fp32_valu": 0.0, "bytes": 0.0}
+
+
+def time_bound(w: dict) -> tuple[float, str]:
+    """Lower bound on the time of one sample's work and the resource that
+    sets it: the matrix pipe (FP64 and BF16 products), the vector ALU (FP64
+    and FP32 operations) and HBM run side by side."""
+    t = {"mfma": w["fp64_mfma"] / PEAK_FP64 + w["bf16_mfma"] / PEAK_BF16_MFMA,
+         "alu": w["fp64_valu"] / PEAK_FP64 + w["fp32_valu"] / PEAK_FP32,
+         "hbm": w["bytes"] / PEAK_HBM}
+    b = max(t, key=t.get)
+    return t[b], b
 
 
 def time_form(T, ctx, F, c, precision, steps, warmup):
@@ -123,47 +193,115 @@ def kernel_digest() -> str:
     return h.hexdigest()[:16]
 
 
+def kind_figures(kind, w, samples_per_launch, avg_s, tr):
+    """Roofline figures of one kernel kind: the lower bound of one launch's
+    time (the slowest of the matrix pipe, the vector ALU and HBM for its
+    algorithmic work), its fraction of the measured average launch time,
+    the rate on the binding resource, and the HBM rate from the measured
+    traffic where current."""
+    tl, bound = time_bound(w)
+    t_launch = tl * samples_per_launch
+    peak = {"mfma": (PEAK_BF16_MFMA if w["bf16_mfma"] > 0 else PEAK_FP64) / 1e12, "alu": PEAK_FP64 / 1e12,
+            "hbm": PEAK_HBM / 1e9}[bound]
+    frac = t_launch / avg_s
+    out = {"bound": bound, "frac": frac, "peak": peak, "achieved": frac * peak,
+           "unit": "GB/s" if bound == "hbm" else "TFLOP/s", "avg_launch_ms": 1e3 * avg_s,
+           "lower_bound_ms": 1e3 * t_launch,
+           "alg_bytes_per_launch": w["bytes"] * samples_per_launch,
+           "alg_hbm_tb_per_s": w["bytes"] * samples_per_launch / avg_s / 1e12,
+           "traffic": tr, "hbm_tb_per_s": (tr / avg_s / 1e12) if tr else None}
+    if kind == "sweep":
+        # the exact row products alone, every flop priced at the FP64 peak
+        out["frac_rows_only"] = w["rows"] * samples_per_launch / PEAK_FP64 / avg_s
+        out["cphi_per_variable"] = ({"fp64_ops": w["cphi"]["f64"], "fp32_ops": w["cphi"]["f32"],
+                                     "source": "rocprofv3 SQ_INSTS_VALU_* counters, profiles/sweep_valu_ops_n16384.md"}
+                                    if w["cphi"] else None)
+    if w["bf16_mfma"] > 0:
+        out["bf16_mfma_tflops_executed"] = w["bf16_mfma"] * samples_per_launch / avg_s / 1e12
+        out["tflops_algorithmic"] = w["alg"] * samples_per_launch / avg_s / 1e12
+    return out
+
+
 def roofline_of(T, results, st, c, precision, steps):
-    """Roofline of the kernel kind with the largest busy time.  achieved =
-    algorithmic work per launch / average launch duration (HIP events on the
-    launch's stream); launches on the two worker streams overlap, so the
-    chip-level rate (all launches' work / union of their intervals) is
-    reported beside it."""
+    """Roofline of the kernel kind with the largest busy time (the headline
+    object) and of every kind of the step.  Per launch: achieved = the
+    launch's algorithmic work / its average duration (HIP events on the
+    launch's own stream), expressed as the fraction of the launch time that
+    the binding resource's peak would need.  Launches on the two worker
+    streams overlap, so the chip-level figures (all launches' work / union
+    of their intervals) are given beside them."""
     n, m, samples = c["n"], c["m"], c["N"] * c["M"]
     ks = {k: sum(r["kernel_seconds"][k] for r in results) for k in T.KERNEL_NAMES}
     kb = {k: sum(r["kernel_busy_seconds"][k] for r in results) for k in T.KERNEL_NAMES}
     kl = {k: sum(r["kernel_launches"][k] for r in results) for k in T.KERNEL_NAMES}
-    dom = max(kb, key=kb.get)
-    work, bound, peak = kernel_work(dom, st, n, m, precision)
-    launches = max(kl[dom], 1)
-    per_launch = work * samples * steps / launches
-    avg = ks[dom] / launches
-    achieved = per_launch / avg
-    chip = work * samples * steps / kb[dom]
-    tr = TRAFFIC.get((c["id"], dom, precision))
-    traffic = tr["bytes_per_launch"] if tr and tr["digest"] == kernel_digest() else None
-    # the same figures for every kernel kind of the step (HBM rate from the
-    # measured traffic where it is current)
     kinds = {}
     for k in ("sweep", "delta", "zproj"):
         if kl[k] == 0 or ks[k] <= 0:
             continue
-        w_k, b_k, p_k = kernel_work(k, st, n, m, precision)
-        pl = w_k * samples * steps / kl[k]
-        av = ks[k] / kl[k]
+        w = kernel_work(k, st, n, m, precision)  # per sample, all tiles
+        # a launch covers one tile of one chunk: its share of the step's work
+        # is the per-sample work times samples x steps / launches
+        spl = samples * steps / kl[k]
         t_k = TRAFFIC.get((c["id"], k, precision))
         tb = t_k["bytes_per_launch"] if t_k and t_k["digest"] == kernel_digest() else None
-        kinds[k] = {"bound": b_k, "achieved": pl / av / 1e12, "peak": p_k / 1e12, "frac": pl / av / p_k,
-                    "avg_launch_ms": 1e3 * av, "traffic": tb,
-                    "hbm_tb_per_s": (tb / av / 1e12) if tb else None}
-    return {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": traffic, "traffic_unit": "bytes/launch",
-            "kernel": dom, "work_per_launch_tflop": per_launch / 1e12, "avg_launch_ms": 1e3 * avg,
-            "achieved_chip": chip / 1e12, "frac_chip": chip / peak,
-            "busy_ms_per_step": {k: 1e3 * v / steps for k, v in kb.items()},
-            "launch_ms_sum_per_step": {k: 1e3 * v / steps for k, v in ks.items()},
-            "launches_per_step": {k: kl[k] // steps for k in kl},
-            "kinds": kinds}
+        kinds[k] = kind_figures(k, w, spl, ks[k] / kl[k], tb)
+        kinds[k]["chip_frac"] = time_bound(w)[0] * samples * steps / kb[k]
+    dom = max(("sweep", "delta", "zproj"), key=lambda k: kb[k])
+    head = dict(kinds[dom])
+    head.update({"kernel": dom, "traffic_unit": "bytes/launch",
+                 "busy_ms_per_step": {k: 1e3 * v / steps for k, v in kb.items()},
+                 "launch_ms_sum_per_step": {k: 1e3 * v / steps for k, v in ks.items()},
+                 "launches_per_step": {k: kl[k] // steps for k in kl},
+                 "kinds": kinds})
+    return head
+
+
+def log_gap_over_se(res, ref):
+    """|P - P_ref| / SE_ref from the logs (the probabilities may be below the double range)."""
+    if not (np.isfinite(res["log_p"]) and np.isfinite(ref["log_p"])) or not ref["rel_err"] > 0:
+        return None
+    return abs(math.expm1(res["log_p"] - ref["log_p"])) / ref["rel_err"]
+
+
+def measure_config(T, ctx, cid, steps, warmup, steps64):
+    """Both forms on one workload: throughput, roofline per kernel kind, the
+    precision form's error against the FP64 form, setup."""
+    import synth
+    import torch
+    c = synth.config(cid)
+    n, N, M = c["n"], c["N"], c["M"]
+    cov = {"xy": c["xy"], "beta": c["beta"]}
+    t0 = time.perf_counter()
+    perm = T.block_reorder(cov, c["a"], c["b"], c["m"]) if c["reorder"] else None
+    F = T.Factor.build(ctx, cov, n, c["m"], c["tol"], c["cap"], perm=perm)
+    setup = time.perf_counter() - t0
+    st = F.stats()
+    torch.cuda.empty_cache()
+    out = {"workload": workload_name(c, c["precision"]), "n": n, "m": c["m"], "samples": N, "shifts": M,
+           "k_tot": st["k_tot"], "k_max": st["k_max"], "cap_hits": st["cap_hits"], "host_tiles": st["host_tiles"],
+           "factor_mb": st["device_bytes"] / 2 ** 20, "setup_s": setup, "setup_phases_s": st["setup_seconds"]}
+    forms = {}
+    for prec in ((1, 0) if c["precision"] == 1 else (0,)):
+        k = steps if prec == 1 else steps64
+        el, lat, res = time_form(T, ctx, F, c, prec, k, warmup)
+        forms[prec] = res[-1]
+        out["precision_form" if prec == 1 else "fp64_form"] = {
+            "value": N * M * n / (el / k), "ms_per_step": 1e3 * el / k, "steps": k,
+            "log_p": res[-1]["log_p"], "std_err": res[-1]["std_err"], "rel_err": res[-1]["rel_err"],
+            "roofline_kinds": roofline_of(T, res, st, c, prec, k)["kinds"]}
+    if 1 in forms:
+        out["ratio_vs_fp64_form"] = out["precision_form"]["value"] / out["fp64_form"]["value"]
+        out["precision_form"]["err_vs_fp64"] = log_gap_over_se(forms[1], forms[0])
+    F.free()
+    torch.cuda.empty_cache()
+    return out
+
+
+def workload_name(c, precision):
+    nu = c["nu"]
+    return (f"{c['name']}: {c['g']}x{c['g']} grid, range {c['beta']}, {'MVT nu ' + str(nu) if nu else 'MVN'}, "
+            f"m {c['m']}, tol {c['tol']}, cap {c['cap']}, reorder {c['reorder']}, N {c['N']} x {c['M']} shifts, "
+            f"{'FP64' if precision == 0 else 'BF16x3-MFMA low-rank, FP32 special functions, FP64 row products and sums'}")
 
 
 def main():
@@ -192,50 +330,67 @@ def main():
     st = F.stats()
     torch.cuda.empty_cache()
 
+    note(f"factor of {c['name']} built in {setup_s:.2f} s; timing {args.steps} steps")
     elapsed, lat, results = time_form(T, ctx, F, c, precision, args.steps, args.warmup)
     ms_per_step = 1e3 * elapsed / args.steps
+    note(f"{ms_per_step:.2f} ms per step")
     value = N * M * n / (elapsed / args.steps)
     roof = roofline_of(T, results, st, c, precision, args.steps)
     dev_s = float(np.mean([r["seconds"] for r in results]))
 
     fp64 = None
     if precision != 0 and not args.no_fp64_form:
-        e64, lat64, res64 = time_form(T, ctx, F, c, 0, max(2, args.steps // 2), 1)
         s64 = max(2, args.steps // 2)
+        e64, lat64, res64 = time_form(T, ctx, F, c, 0, s64, 1)
         r64 = res64[-1]
+        roof64 = roofline_of(T, res64, st, c, 0, s64)
         fp64 = {"value": N * M * n / (e64 / s64), "ms_per_step": 1e3 * e64 / s64, "log_p": r64["log_p"],
-                "std_err": r64["std_err"], "rel_err": r64["rel_err"],
-                "roofline": roofline_of(T, res64, st, c, 0, s64)}
+                "std_err": r64["std_err"], "rel_err": r64["rel_err"], "roofline": roof64,
+                "note": "the ratio is against this form: same factor, points and kernels' structure, all FP64; "
+                        "its limit update runs on FP64 matrix cores and its projection on the FP64 vector ALU, "
+                        "at the fractions of their bounds given in roofline.kinds"}
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline(F, c, args.cpu_samples)
+    if fp64:
+        note(f"FP64 form {fp64['ms_per_step']:.2f} ms per step")
+    cpu = None if args.no_cpu_baseline else cpu_baseline(F, c, args.cpu_samples, args.cpu_samples_1t)
+    if cpu:
+        note(f"CPU oracle {cpu['value']:.3g} sample-dims/s")
     F.free()
     torch.cuda.empty_cache()
+    extra = {}
+    for cid in [int(x) for x in args.extra_configs.split(",") if x.strip()]:
+        if cid != args.config:
+            extra[str(cid)] = measure_config(T, ctx, cid, 3, 1, 2)
+            note(f"workload {cid} done")
     serve = serving(T, ctx, args.serve, args.serve_fp64, args.serve_budget_gib) if args.serve > 0 else None
+    if serve:
+        note(f"serving p50 {serve['latency_ms']['p50']:.0f} ms p99 {serve['latency_ms']['p99']:.0f} ms")
     study = None if args.no_reorder_study else reorder_study(T, ctx)
     client = None if args.no_reorder_study else skewnormal_client(T, ctx)
     r0 = results[-1]
     lat_ms = [1e3 * x for x in lat]
+    est = {"log_p": r0["log_p"], "std_err": r0["std_err"], "rel_err": r0["rel_err"]}
+    if fp64:
+        est["err_vs_fp64"] = log_gap_over_se(r0, {"log_p": fp64["log_p"], "rel_err": fp64["rel_err"]})
     out = {
         "metric": METRIC, "value": value, "unit": "sample·dims/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if precision == 0 else "f64+bf16",
+        "dtype": "f64" if precision == 0 else "f64+fp32+bf16",
         "data": "synthetic (seeded grid, limits and shifts)",
-        "config": {"workload": f"{c['name']}: {c['g']}x{c['g']} grid, range {c['beta']}, "
-                               f"{'MVT nu ' + str(nu) if nu else 'MVN'}, m {m}, tol {c['tol']}, "
-                               f"cap {c['cap']}, reorder {c['reorder']}, N {N} x {M} shifts, "
-                               f"{'FP64' if precision == 0 else 'BF16x3-MFMA low-rank / FP64 sweep'}",
+        "config": {"workload": workload_name(c, precision),
                    "n": n, "m": m, "samples": N, "shifts": M, "precision": precision,
                    "k_tot": st["k_tot"], "k_max": st["k_max"], "cap_hits": st["cap_hits"],
                    "factor_mb": st["device_bytes"] / 2 ** 20, "setup_s": setup_s,
                    "setup_phases_s": st["setup_seconds"], "host_tiles": st["host_tiles"]},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
-        "estimate": {"log_p": r0["log_p"], "std_err": r0["std_err"], "rel_err": r0["rel_err"]},
+        "estimate": est,
         "value_device_only": N * M * n / dev_s,
         "fp64_form": fp64,
         "ratio_vs_fp64_form": (value / fp64["value"]) if fp64 else None,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "other_configs": extra,
         "serving": serve,
         "reorder_study": study,
         "skewnormal_client": client,
@@ -254,7 +409,9 @@ def serving(T, ctx, count: int, count_fp64: int, budget_gib: float):
     S = T.Server(ctx, int(budget_gib * 2 ** 30))
     t0 = time.perf_counter()
     tickets = []
-    for q in reqs:
+    for i, q in enumerate(reqs):
+        if i % 400 == 0:
+            note(f"serving: submitting request {i} of {count}")
         delay = q["arrival"] - (time.perf_counter() - t0)
         if delay > 0:
             time.sleep(delay)
@@ -271,8 +428,11 @@ def serving(T, ctx, count: int, count_fp64: int, budget_gib: float):
     span = max(i["t_done"] for i in info) - min(i["t_submit"] for i in info)
     work = float(sum(q["N"] * q["M"] * q["n"] for q in reqs))
     res = {"requests": count, "rate_per_s": 20.0, "budget_gib": budget_gib,
-           "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)), "p99": 1e3 * float(np.percentile(lat, 99)),
+           "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)), "p90": 1e3 * float(np.percentile(lat, 90)),
+                          "p99": 1e3 * float(np.percentile(lat, 99)), "max": 1e3 * float(lat.max()),
                           "mean": 1e3 * float(lat.mean())},
+           "p99_ms_by_n": {str(g * g): 1e3 * float(np.percentile([x for x, q in zip(lat, reqs) if q["g"] == g], 99))
+                           for g in (32, 64, 96, 128) if any(q["g"] == g for q in reqs)},
            "phase_ms_mean": {"queue": 1e3 * float(queue.mean()), "setup": 1e3 * float(setup.mean()),
                              "run": 1e3 * float(run.mean())},
            "run_ms": {"p50": 1e3 * float(np.percentile(run, 50)), "p99": 1e3 * float(np.percentile(run, 99))},
@@ -363,24 +523,35 @@ def copy_calibration(torch, mib: int):
     print(json.dumps({"copy_calibration": {"bytes_read": 4 * n, "bytes_written": 4 * n, "launches": 3}}), flush=True)
 
 
-def cpu_baseline(F, c, S: int):
-    """The oracle (dense SOV on the expanded factor) on the host, S points of shift 0."""
+def cpu_baseline(F, c, S: int, S1: int):
+    """The oracle (dense SOV on the expanded factor) on the host: S points of
+    shift 0 with every thread its BLAS takes, and S1 points on one thread."""
     import oracle
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
     except Exception:
+        threadpool_limits = None
         threads = os.cpu_count()
     perm, diag, ranks, U, V = F.export()
     fac = (diag, ranks, U, V)
     ap, bp = c["a"][perm], c["b"][perm]
-    t0 = time.perf_counter()
     lat = oracle.api.Lattice(c["n"], c["M"], c["seed_shift"])
+    t0 = time.perf_counter()
     oracle.sample_logp(fac, ap, bp, c["nu"], c["seed_shift"], c["M"], 0, np.arange(1, S + 1), lat)
     t = time.perf_counter() - t0
-    return {"value": S * c["n"] / t, "unit": "sample·dims/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{S} lattice points of shift 0 of the same workload (dense SOV over the expanded "
-                      f"factor, numpy/scipy), {t:.1f} s"}
+    out = {"value": S * c["n"] / t, "unit": "sample·dims/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"{S} lattice points of shift 0 of the same workload (dense SOV over the expanded "
+                     f"factor, numpy/scipy, {int(threads)} threads), {t:.1f} s; per-sample cost is the same "
+                     f"for every point, so the rate holds for the whole N x M"}
+    if S1 > 0 and threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            oracle.sample_logp(fac, ap, bp, c["nu"], c["seed_shift"], c["M"], 0, np.arange(1, S1 + 1), lat)
+            t1 = time.perf_counter() - t0
+        out["single_thread"] = {"value": S1 * c["n"] / t1, "cores": 1,
+                                "sample": f"{S1} lattice points of shift 0, one thread, {t1:.1f} s"}
+    return out
 
 
 if __name__ == "__main__":

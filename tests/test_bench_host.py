@@ -20,23 +20,46 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in out["error"]
 
 
+def test_sweep_row_flops_are_the_triangles():
+    # every tile contributes m_i (m_i - 1) flops of row products; rows inside
+    # 16-row blocks on the vector ALU, earlier blocks on matrix cores
+    mf, va = bench.sweep_row_flops(16384, 256)
+    assert mf + va == 64 * 256 * 255 and va == 64 * 16 * 16 * 15
+    mf, va = bench.sweep_row_flops(1000, 256)  # ragged last tile of 232 rows (14 blocks of 16 and one of 8)
+    assert mf + va == 3 * 256 * 255 + 232 * 231 and va == 3 * 16 * 240 + 14 * 240 + 8 * 7
+
+
 def test_kernel_work_per_sample():
     n, m, k_tot = 16384, 256, 17195
     st = {"k_tot": k_tot}
-    # sweep: the row products of every diagonal tile plus the per-variable cost
-    w, bound, peak = bench.kernel_work("sweep", st, n, m, 1)
-    assert w == 64 * m * (m - 1) + bench.C_PHI * n and bound == "alu" and peak == bench.PEAK_FP64_VALU
-    # ragged last tile
-    w, _, _ = bench.kernel_work("sweep", st, 1000, 256, 1)
-    assert w == 3 * 256 * 255 + 232 * 231 + bench.C_PHI * 1000
-    # low-rank products: 2 m K_tot per sample, three BF16 products in the precision form
+    w = bench.kernel_work("sweep", st, n, m, 1)
+    assert w["rows"] == 64 * m * (m - 1)
+    assert w["bytes"] == 8 * n + 24 * 64
+    # low-rank products: 2 m K_tot per sample, three BF16 products executed in the precision form
     for kind in ("delta", "zproj"):
-        w, bound, peak = bench.kernel_work(kind, st, n, m, 1)
-        assert w == 3 * 2.0 * m * k_tot and bound == "mfma" and peak == bench.PEAK_BF16_MFMA
-    w, bound, peak = bench.kernel_work("delta", st, n, m, 0)
-    assert w == 2.0 * m * k_tot and bound == "mfma" and peak == bench.PEAK_FP64_VALU
-    w, bound, peak = bench.kernel_work("zproj", st, n, m, 0)
-    assert w == 2.0 * m * k_tot and bound == "alu" and peak == bench.PEAK_FP64_VALU
+        w = bench.kernel_work(kind, st, n, m, 1)
+        assert w["bf16_mfma"] == 3 * 2.0 * m * k_tot and w["alg"] == 2.0 * m * k_tot
+        assert w["bytes"] == 4 * (k_tot + n)
+    w = bench.kernel_work("delta", st, n, m, 0)
+    assert w["fp64_mfma"] == 2.0 * m * k_tot and w["fp64_valu"] == 0.0
+    w = bench.kernel_work("zproj", st, n, m, 0)
+    assert w["fp64_valu"] == 2.0 * m * k_tot and w["fp64_mfma"] == 0.0
+
+
+def test_time_bound_takes_the_slowest_resource():
+    w = {"fp64_mfma": 78.6e12, "bf16_mfma": 0.0, "fp64_valu": 2 * 78.6e12, "fp32_valu": 157.3e12, "bytes": 8e12}
+    t, b = bench.time_bound(w)
+    assert b == "alu" and abs(t - 3.0) < 1e-12
+    w = {"fp64_mfma": 0.0, "bf16_mfma": 2.5e15, "fp64_valu": 0.0, "fp32_valu": 0.0, "bytes": 16e12}
+    t, b = bench.time_bound(w)
+    assert b == "hbm" and abs(t - 2.0) < 1e-12
+
+
+def test_log_gap_over_se():
+    import math
+    # P = 1.1 e^-500 against 1.0 e^-500 with relative error 0.2: (0.1) / 0.2
+    g = bench.log_gap_over_se({"log_p": math.log(1.1) - 500}, {"log_p": -500.0, "rel_err": 0.2})
+    assert abs(g - 0.5) < 1e-12
 
 
 def test_traffic_table_keys():
