@@ -181,7 +181,7 @@ TRAFFIC = {
 }
 KERNEL_SOURCES = tuple(os.path.join("csrc", f) for f in (
     "kernels.hip", "kernels_mfma.hip", "kernels_lr64.hip", "device_math.hpp", "special_tables.hpp",
-    "internal.hpp")) + ("build.py",)
+    "internal.hpp", "plan.hpp")) + ("build.py",)
 
 
 def kernel_digest() -> str:

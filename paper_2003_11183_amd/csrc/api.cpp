@@ -77,13 +77,6 @@ void estimate_from_parts(const std::vector<double> &part, int M, int64_t N, tlrq
 namespace {
 
 
-// Samples per call from which the chunks run on worker streams, the number
-// of worker streams, and the device memory the chunk buffers may take.
-constexpr int64_t kMultiStreamSamples = 131072;
-constexpr int kWorkerStreams = 2;
-constexpr int64_t kScratchBudget = int64_t{64} << 30;
-constexpr int64_t kMaxChunk = int64_t{1} << 22;
-
 // HIP events around launches (on the launch's own stream), summed per
 // kernel kind.
 struct Profiler {
@@ -233,32 +226,18 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
   // rows).  Large runs are split over two worker streams so that their
   // launches overlap (see tlrqmc_ctx::workers).
   const bool prec = opts->precision == 1;
-  const int64_t mpad = round_up(f->m, 64);
-  const int64_t per_sample = prec ? 4 * f->zp_tot + 8 * mpad + 16 : 8 * (f->k_tot + 2 * mpad + 2);
-  const int nstream = (!fixed && count >= kMultiStreamSamples) ? kWorkerStreams : 1;
-  int64_t chunk = opts->chunk_samples;
-  if (fixed) {
-    // what is left of the region after the per-call arrays, in chunks of 256
-    const int64_t fixed_bytes = (two_sided ? round_up(8 * n, 256) : 0) + round_up(8 * n, 256) +
-                                round_up(8 * static_cast<int64_t>(M) * (n + 1), 256) + round_up(8 * count, 256) +
-                                (reduce ? round_up(8 * 3 * M, 256) : 0);
-    const int64_t room = static_cast<int64_t>(fixed->left) - fixed_bytes - 5 * 256;
-    const int64_t fit = room > 0 ? room / per_sample / 256 * 256 : 0;
-    if (fit < 256)
-      return fail(TLRQMC_ENOMEM,
-                  "the problem does not fit the %lld MiB no-allocation scratch (n = %lld, %lld samples: %lld bytes "
-                  "of per-call arrays plus %lld per sample, chunks of at least 256 samples)",
-                  static_cast<long long>(noalloc_scratch_bytes() >> 20), static_cast<long long>(n),
-                  static_cast<long long>(count), static_cast<long long>(fixed_bytes),
-                  static_cast<long long>(per_sample));
-    chunk = chunk > 0 ? std::min(chunk, fit) : fit;
-  } else if (chunk <= 0) {
-    const int64_t budget = kScratchBudget / nstream;
-    chunk = std::max<int64_t>(256, std::min<int64_t>(budget / per_sample, (count + nstream - 1) / nstream));
-  }
-  // at most 2^22 samples per chunk: the low-rank kernels address 32 rows of
-  // a chunk buffer with 32-bit byte offsets
-  chunk = round_up(std::min({chunk, count, kMaxChunk}), 256);
+  const int64_t call_bytes = estimator_call_bytes(n, M, count, two_sided, reduce);
+  const ChunkPlan cp = plan_chunks(f, prec, count, opts->chunk_samples, fixed ? static_cast<int64_t>(fixed->left) : -1,
+                                   call_bytes);
+  if (cp.chunk == 0)
+    return fail(TLRQMC_ENOMEM,
+                "the problem does not fit the %lld MiB no-allocation scratch (n = %lld, %lld samples: %lld bytes "
+                "of per-call arrays plus %lld per sample, chunks of at least 256 samples)",
+                static_cast<long long>(noalloc_scratch_bytes() >> 20), static_cast<long long>(n),
+                static_cast<long long>(count), static_cast<long long>(call_bytes),
+                static_cast<long long>(chunk_bytes_per_sample(f, prec)));
+  const int nstream = cp.nstream;
+  const int64_t chunk = cp.chunk;
   const int64_t ld = chunk;
   SharedDevice dev;  // no library factorization runs beside these kernels
   Scratch sc(ctx);
@@ -272,25 +251,28 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
     return fail(TLRQMC_ENOMEM, "device allocation failed");
   struct Lane {
     hipStream_t s;
-    void *Y;  // FP32 in the precision form
-    double *Dl, *Z, *R;
-    float *DlF, *ZF;
+    ChunkBuffers b;
   };
   std::vector<Lane> lanes(nstream);
   if (nstream > 1 && ctx->worker_streams(nstream) != TLRQMC_OK) return TLRQMC_EDEVICE;
+  int64_t lane_bytes[4];
+  chunk_buffer_bytes(f, prec, nu > 0, ld, lane_bytes);
   for (int w = 0; w < nstream; ++w) {
     Lane &L = lanes[w];
     L.s = nstream > 1 ? ctx->workers[w] : ctx->stream;
-    const size_t cols = static_cast<size_t>(ld);
-    L.Y = take((prec ? 4 : 8) * static_cast<size_t>(mpad) * cols);
-    L.Dl = (!prec && r > 1) ? static_cast<double *>(take(8 * static_cast<size_t>(mpad) * cols)) : nullptr;
-    L.Z = (!prec && f->k_tot > 0) ? static_cast<double *>(take(8 * static_cast<size_t>(f->k_tot) * cols)) : nullptr;
-    L.DlF = (prec && r > 1) ? static_cast<float *>(take(4 * static_cast<size_t>(mpad) * cols)) : nullptr;
-    L.ZF = (prec && f->k_tot > 0) ? static_cast<float *>(take(4 * static_cast<size_t>(f->zp_tot) * cols)) : nullptr;
-    L.R = nu > 0 ? static_cast<double *>(take(8 * cols)) : nullptr;
-    if (!L.Y || (!prec && r > 1 && !L.Dl) || (!prec && f->k_tot > 0 && !L.Z) || (prec && r > 1 && !L.DlF) ||
-        (prec && f->k_tot > 0 && !L.ZF) || (nu > 0 && !L.R))
-      return fail(TLRQMC_ENOMEM, "device allocation failed (chunk of %lld samples)", static_cast<long long>(chunk));
+    void *got[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (int k = 0; k < 4; ++k)
+      if (lane_bytes[k] > 0 && !(got[k] = take(static_cast<size_t>(lane_bytes[k]))))
+        return fail(TLRQMC_ENOMEM, "device allocation failed (chunk of %lld samples)", static_cast<long long>(chunk));
+    L.b.Y = got[0];
+    L.b.R = static_cast<double *>(got[3]);
+    if (prec) {
+      L.b.DlF = static_cast<float *>(got[1]);
+      L.b.ZF = static_cast<float *>(got[2]);
+    } else {
+      L.b.Dl = static_cast<double *>(got[1]);
+      L.b.Z = static_cast<double *>(got[2]);
+    }
   }
   const std::vector<uint64_t> shifts = splitmix64_table(opts->seed, static_cast<int64_t>(M) * (n + 1));
   hipStream_t st = ctx->stream;
@@ -322,68 +304,49 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
       if (c0 < count) cs.push_back({c0, std::min(chunk, count - c0)});
     }
     chunks += static_cast<int>(cs.size());
+    std::vector<ChunkRun> runs;
+    for (size_t w = 0; w < cs.size(); ++w)
+      runs.push_back(ChunkRun{g0 + cs[w].first, cs[w].second, N, ld, prec, lanes[w].b, d_a, d_b, d_D,
+                              d_logp + cs[w].first});
     for (size_t w = 0; w < cs.size(); ++w) {
       const Lane &L = lanes[w];
-      InitParams ip{g0 + cs[w].first, cs[w].second, N, f->d_gen, d_D, n + 1, nu, d_logp + cs[w].first, L.R};
       prof.begin(TLRQMC_KERNEL_INIT, L.s);
-      launch_init(L.s, ip);
+      launch_init(L.s, init_launch(f, runs[w], nu));
       prof.end(L.s);
       if (!check_launch("init")) return fail_device(ctx, lanes.size());
     }
     for (int j = 0; j < r; ++j) {
       for (size_t w = 0; w < cs.size(); ++w) {
         const Lane &L = lanes[w];
-        const int64_t c0 = cs[w].first, cnt = cs[w].second;
-        const bool has_delta = j > 0 && f->krow[j] > 0;
-        if (has_delta) {
+        const TileLaunch t = tile_launch(f, j, runs[w]);
+        if (t.delta) {
           prof.begin(TLRQMC_KERNEL_DELTA, L.s);
-          if (prec) {
-            const unsigned short *u = f->d_ubf + f->ubf_off[j];
-            MfmaLrParams mp{cnt, ld, f->tm[j], static_cast<int>(f->krow[j]), f->kp_row[j], u,
-                            u + f->ubf_size[j], L.ZF + f->zoffp[j] * ld, nullptr, nullptr, L.DlF};
-            launch_lr_mfma(L.s, mp);
-          } else {
-            LrParams lp{cnt, ld, f->tm[j], static_cast<int>(f->krow[j]), f->urow_ld[j],
-                        f->d_urow + f->urow_off[j], L.Z + f->zoff[j] * ld, L.Dl, nullptr};
-            launch_delta_f64(L.s, lp);
-          }
+          if (prec) launch_lr_mfma(L.s, t.delta_mfma);
+          else launch_delta_f64(L.s, t.delta_f64);
           prof.end(L.s);
           if (!check_launch("delta")) return fail_device(ctx, lanes.size());
         }
-        SweepParams sp{g0 + c0, cnt, N, ld, n + 1, f->tm[j], static_cast<int>(1 + f->toff[j]),
-                       f->d_diag + f->diag_off[j], two_sided ? d_a + f->toff[j] : nullptr,
-                       d_b + f->toff[j],
-                       has_delta ? (prec ? static_cast<const void *>(L.DlF) : static_cast<const void *>(L.Dl)) : nullptr,
-                       L.R, f->d_gen, d_D, d_logp + c0, L.Y};
         prof.begin(TLRQMC_KERNEL_SWEEP, L.s);
-        launch_sweep(L.s, sp, two_sided, nu > 0, prec);
+        launch_sweep(L.s, t.sweep, two_sided, nu > 0, prec);
         prof.end(L.s);
         if (!check_launch("sweep")) return fail_device(ctx, lanes.size());
-        if (j < r - 1 && f->kcol[j] > 0) {
+        if (t.zproj) {
           prof.begin(TLRQMC_KERNEL_ZPROJ, L.s);
-          if (prec) {
-            const unsigned short *v = f->d_vbf + f->vbf_off[j];
-            MfmaLrParams zp{cnt, ld, static_cast<int>(f->kcol[j]), f->tm[j], f->vbf_mp[j], v,
-                            v + f->vbf_size[j], static_cast<const float *>(L.Y), nullptr,
-                            f->d_zmapp + f->zmap_off[j], L.ZF};
-            launch_lr_mfma(L.s, zp);
-          } else {
-            LrParams lp{cnt, ld, static_cast<int>(f->kcol[j]), f->tm[j], f->vpan_ld[j],
-                        f->d_vpan + f->vpan_off[j], static_cast<const double *>(L.Y), L.Z,
-                        f->d_zmap + f->zmap_off[j]};
-            launch_zproj_f64(L.s, lp);
-          }
+          if (prec) launch_lr_mfma(L.s, t.zproj_mfma);
+          else launch_zproj_f64(L.s, t.zproj_f64);
           prof.end(L.s);
           if (!check_launch("zproj")) return fail_device(ctx, lanes.size());
         }
       }
     }
   }
+  // the context stream waits for the workers (the host does, if the event
+  // cannot be made): every later free happens after its kernels ended
   if (nstream > 1)
     for (auto &L : lanes) {
       hipEvent_t e = evs.make();
-      (void)hipEventRecord(e, L.s);
-      (void)hipStreamWaitEvent(st, e, 0);
+      if (!e || hipEventRecord(e, L.s) != hipSuccess || hipStreamWaitEvent(st, e, 0) != hipSuccess)
+        if (hipStreamSynchronize(L.s) != hipSuccess) return fail_device(ctx, lanes.size());
     }
   if (reduce) {
     ReduceParams rp{N, M, d_logp, d_part};
@@ -458,7 +421,7 @@ void tlrqmc_ctx::release_pinned() {
 void tlrqmc_ctx::dfree(void *p) {
   if (!p) return;
   if (has_alloc) alloc.free(p, alloc.user);
-  else hipFree(p);
+  else (void)hipFree(p);
 }
 
 extern "C" {
@@ -540,8 +503,8 @@ int tlrqmc_factor_export(const tlrqmc_factor *f, int32_t *perm, double *diag, in
 void tlrqmc_factor_free(tlrqmc_factor *f) {
   if (!f) return;
   if (f->ctx) {
-    hipSetDevice(f->ctx->device);
-    hipStreamSynchronize(f->ctx->stream);
+    (void)hipSetDevice(f->ctx->device);
+    (void)hipStreamSynchronize(f->ctx->stream);
     f->ctx->dfree(f->d_diag);
     f->ctx->dfree(f->d_urow);
     f->ctx->dfree(f->d_vpan);

@@ -55,9 +55,6 @@ int build_impl(tlrqmc_ctx *ctx, int64_t n, int m, const int32_t *perm, const dou
   auto f = new tlrqmc_factor();
   std::unique_ptr<tlrqmc_factor, void (*)(tlrqmc_factor *)> guard(f, tlrqmc_factor_free);
   f->ctx = ctx;
-  f->n = n;
-  f->m = m;
-  f->r = r;
   f->cap_hits = cap_hits;
   f->perm.resize(n);
   if (perm) {
@@ -71,34 +68,19 @@ int build_impl(tlrqmc_ctx *ctx, int64_t n, int m, const int32_t *perm, const dou
   } else {
     std::iota(f->perm.begin(), f->perm.end(), 0);
   }
-  f->tm.resize(r);
-  f->toff.resize(r + 1);
-  for (int i = 0; i < r; ++i) {
-    f->toff[i] = static_cast<int64_t>(i) * m;
-    f->tm[i] = static_cast<int>(std::min<int64_t>(m, n - f->toff[i]));
-  }
-  f->toff[r] = n;
-  // ranks and the derived widths
-  f->rank.assign(static_cast<size_t>(r) * r, 0);
-  f->krow.assign(r, 0);
-  f->kcol.assign(r, 0);
+  // ranks, then the tile geometry and the derived widths
+  auto rows_of = [&](int i) { return static_cast<int>(std::min<int64_t>(m, n - static_cast<int64_t>(i) * m)); };
   int64_t uv_doubles_u = 0, uv_doubles_v = 0;
   for (int i = 1; i < r; ++i)
     for (int j = 0; j < i; ++j) {
       const int k = ranks[static_cast<size_t>(i) * r + j];
-      if (k < 0 || k > std::min(f->tm[i], f->tm[j]))
+      if (k < 0 || k > std::min(rows_of(i), rows_of(j)))
         return fail(TLRQMC_EINVAL, "rank of tile (%d,%d) out of range: %d", i, j, k);
       if (k > 0 && (!U || !V)) return fail(TLRQMC_EINVAL, "U and V are required for nonzero ranks");
-      f->rank[static_cast<size_t>(i) * r + j] = k;
-      f->krow[i] += k;
-      f->kcol[j] += k;
-      f->k_max = std::max(f->k_max, k);
-      uv_doubles_u += static_cast<int64_t>(f->tm[i]) * k;
-      uv_doubles_v += static_cast<int64_t>(f->tm[j]) * k;
+      uv_doubles_u += static_cast<int64_t>(rows_of(i)) * k;
+      uv_doubles_v += static_cast<int64_t>(rows_of(j)) * k;
     }
-  f->zoff.assign(r + 1, 0);
-  for (int i = 0; i < r; ++i) f->zoff[i + 1] = f->zoff[i] + f->krow[i];
-  f->k_tot = f->zoff[r];
+  factor_geometry(f, n, m, ranks);
   if (f->k_tot > (int64_t{1} << 31) - 1) return fail(TLRQMC_EINVAL, "total rank too large");
   // host exchange copies (validated)
   int64_t diag_doubles = 0;
@@ -150,12 +132,7 @@ int build_impl(tlrqmc_ctx *ctx, int64_t n, int m, const int32_t *perm, const dou
   // independent).
   constexpr int SB = kSweepBlock;
   std::vector<int64_t> dsrc(r + 1, 0);
-  f->diag_off.assign(r + 1, 0);
-  for (int i = 0; i < r; ++i) {
-    const int nb = (f->tm[i] + SB - 1) / SB;
-    dsrc[i + 1] = dsrc[i] + static_cast<int64_t>(f->tm[i]) * f->tm[i];
-    f->diag_off[i + 1] = f->diag_off[i] + static_cast<int64_t>(nb) * (nb + 1) / 2 * SB * SB;
-  }
+  for (int i = 0; i < r; ++i) dsrc[i + 1] = dsrc[i] + static_cast<int64_t>(f->tm[i]) * f->tm[i];
   std::vector<int64_t> u_src(static_cast<size_t>(r) * r, 0), v_src(static_cast<size_t>(r) * r, 0);
   {
     int64_t ou = 0, ov = 0;
@@ -168,42 +145,13 @@ int build_impl(tlrqmc_ctx *ctx, int64_t n, int m, const int32_t *perm, const dou
         ov += static_cast<int64_t>(f->tm[j]) * k;
       }
   }
-  f->urow_off.assign(r + 1, 0);
-  f->urow_ld.assign(r, 0);
-  f->vpan_off.assign(r + 1, 0);
-  f->vpan_ld.assign(r, 0);
-  f->zmap_off.assign(r + 1, 0);
-  f->kp_row.assign(r, 0);
-  f->zoffp.assign(r + 1, 0);
-  f->ubf_off.assign(r + 1, 0);
-  f->ubf_size.assign(r, 0);
-  f->vbf_off.assign(r + 1, 0);
-  f->vbf_size.assign(r, 0);
-  f->vbf_mp.assign(r, 0);
-  for (int i = 0; i < r; ++i) {
-    f->urow_ld[i] = static_cast<int>(round_up(f->tm[i], kLrRows));
-    f->urow_off[i + 1] = f->urow_off[i] + static_cast<int64_t>(f->urow_ld[i]) * f->krow[i];
-    f->vpan_ld[i] = static_cast<int>(round_up(std::max<int64_t>(f->kcol[i], 1), kLrRows));
-    f->vpan_off[i + 1] = f->vpan_off[i] + static_cast<int64_t>(f->vpan_ld[i]) * f->tm[i];
-    f->zmap_off[i + 1] = f->zmap_off[i] + f->kcol[i];
-    // precision form: BF16 hi/lo splits and a Z layout with row blocks padded to 32
-    f->kp_row[i] = static_cast<int>(round_up(f->krow[i], 32));
-    f->zoffp[i + 1] = f->zoffp[i] + f->kp_row[i];
-    f->ubf_size[i] = lr_mfma_rows(f->tm[i]) * f->kp_row[i];
-    f->ubf_off[i + 1] = f->ubf_off[i] + 2 * f->ubf_size[i];
-    f->vbf_mp[i] = static_cast<int>(round_up(f->tm[i], 32));
-    f->vbf_size[i] = lr_mfma_rows(static_cast<int>(f->kcol[i])) * f->vbf_mp[i];
-    f->vbf_off[i + 1] = f->vbf_off[i] + 2 * f->vbf_size[i];
-  }
-  f->zp_tot = f->zoffp[r];
+  factor_layout(f);
   // Every device array is laid out directly in one pinned staging buffer
   // (already mapped, so no page faults), cleared in parallel, filled tile by
   // tile, then uploaded.
   const std::vector<uint64_t> gen = richtmyer_generators(n + 1);
-  const size_t sizes[8] = {static_cast<size_t>(f->diag_off[r]) * 8, static_cast<size_t>(f->urow_off[r]) * 8,
-                           static_cast<size_t>(f->vpan_off[r]) * 8, static_cast<size_t>(f->zmap_off[r]) * 4,
-                           gen.size() * 8, static_cast<size_t>(f->ubf_off[r]) * 2,
-                           static_cast<size_t>(f->vbf_off[r]) * 2, static_cast<size_t>(f->zmap_off[r]) * 4};
+  size_t sizes[8];
+  factor_device_sizes(f, sizes);
   size_t offs[9] = {0};
   for (int k = 0; k < 8; ++k) offs[k + 1] = offs[k] + static_cast<size_t>(round_up(static_cast<int64_t>(sizes[k]), 256));
   char *stage = reinterpret_cast<char *>(ctx->pinned(2, offs[8]));
@@ -266,31 +214,25 @@ int build_impl(tlrqmc_ctx *ctx, int64_t n, int m, const int32_t *perm, const dou
           split_bf16(x, hi[t * kp + col], lo[t * kp + col]);
         }
     }
-    // V_panel(i): row-major, columns padded to kLrRows; zmap sends column c
-    // of tile (l, i) to Z row zoff[l] + (ranks of tiles (l, 0..i-1)) + c;
-    // the BF16 split of V_panel^T is row-major with t padded to 32
+    // V_panel(i): row-major, columns padded to kLrRows, tiles (l, i) in
+    // increasing l; the BF16 split of V_panel^T is row-major with t padded
+    // to 32; zmap sends each column to its row of Z
     const int ldv = f->vpan_ld[i];
     double *dv = hv + f->vpan_off[i];
-    int32_t *z = hz + f->zmap_off[i], *zp = hzp + f->zmap_off[i];
     const int64_t mp = f->vbf_mp[i];
     unsigned short *vhi = hvb + f->vbf_off[i], *vlo = vhi + f->vbf_size[i];
     col = 0;
     for (int l = i + 1; l < r; ++l) {
       const int k = f->rank[static_cast<size_t>(l) * r + i];
-      if (k == 0) continue;
-      int64_t zr = f->zoff[l];
-      for (int jj = 0; jj < i; ++jj) zr += f->rank[static_cast<size_t>(l) * r + jj];
       const double *sv = f->h_V.data() + v_src[static_cast<size_t>(l) * r + i];
-      for (int c = 0; c < k; ++c, ++col) {
+      for (int c = 0; c < k; ++c, ++col)
         for (int t = 0; t < mi; ++t) {
           const double x = sv[static_cast<int64_t>(t) * k + c];
           dv[static_cast<int64_t>(t) * ldv + col] = x;
           split_bf16(x, vhi[col * mp + t], vlo[col * mp + t]);
         }
-        z[col] = static_cast<int32_t>(zr + c);
-        zp[col] = static_cast<int32_t>(f->zoffp[l] + (zr + c - f->zoff[l]));
-      }
     }
+    factor_zmaps(f, i, hz + f->zmap_off[i], hzp + f->zmap_off[i]);
   }
   void **dst[8] = {reinterpret_cast<void **>(&f->d_diag), reinterpret_cast<void **>(&f->d_urow),
                    reinterpret_cast<void **>(&f->d_vpan), reinterpret_cast<void **>(&f->d_zmap),

@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "plan.hpp"
 #include "tlrqmc.h"
 
 namespace tlrqmc {
@@ -22,13 +23,6 @@ void clear_error();
 // of empty samples), as the device reduction writes them.
 void estimate_from_parts(const std::vector<double> &part, int M, int64_t N, tlrqmc_result *out);
 
-// Row-block height of the diagonal-tile sweep and the padded row count of a
-// tile in the blocked layout.
-constexpr int kSweepBlock = 16;
-// Rows (delta) / columns (projection) produced per FP64 low-rank pass.
-constexpr int kLrRows = 64;
-
-inline int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
 // Device buffers of one call, released on scope exit (through the context's
 // allocator).
@@ -76,59 +70,15 @@ struct tlrqmc_ctx {
   void release_pinned();
 };
 
-// Device-resident TLR factor.  Host vectors keep the exchange layout for
-// export and the sizes the launches need.
-struct tlrqmc_factor {
-  tlrqmc_ctx *ctx = nullptr;
-  int64_t n = 0;
-  int m = 0, r = 0;
-  std::vector<int32_t> perm;
-  std::vector<int> tm;          // rows of tile i
-  std::vector<int64_t> toff;    // first variable of tile i
-  std::vector<int32_t> rank;    // r x r, rank[i*r+j] for i > j
-  std::vector<int64_t> krow;    // sum_j<i k_ij: width of U_row(i)
-  std::vector<int64_t> kcol;    // sum_i>j k_ij: width of V_panel(j)
-  std::vector<int64_t> zoff;    // first Z row of tile i (prefix of krow)
-  int64_t k_tot = 0;
-  int k_max = 0;
-  int cap_hits = 0;
-  // Host exchange copies.
-  std::vector<double> h_diag, h_U, h_V;
-  // Device layouts.
-  double *d_diag = nullptr;     // blocked diagonal tiles (see kernels)
-  std::vector<int64_t> diag_off;
-  double *d_urow = nullptr;     // U_row(i): column-major, rows padded to kLrRows
-  std::vector<int64_t> urow_off;
-  std::vector<int> urow_ld;
-  double *d_vpan = nullptr;     // V_panel(j): row-major, columns padded to kLrRows
-  std::vector<int64_t> vpan_off;
-  std::vector<int> vpan_ld;
-  int32_t *d_zmap = nullptr;    // V_panel(j) column -> Z row
-  std::vector<int64_t> zmap_off;
-  uint64_t *d_gen = nullptr;    // lattice generators A_0..A_n
-  // Precision form: BF16 hi/lo splits of U_row (row-major, k padded to 32,
-  // rows padded to the MFMA block) and of V_panel^T (row-major, t padded to
-  // 32), and a Z layout whose row blocks are padded to 32.
-  unsigned short *d_ubf = nullptr;
-  std::vector<int64_t> ubf_off;  // hi at off, lo at off + ubf_size[i]
-  std::vector<int64_t> ubf_size;
-  std::vector<int> kp_row;       // round_up(krow, 32)
-  unsigned short *d_vbf = nullptr;
-  std::vector<int64_t> vbf_off;
-  std::vector<int64_t> vbf_size;
-  std::vector<int> vbf_mp;       // round_up(m_j, 32)
-  int32_t *d_zmapp = nullptr;    // V_panel(j) column -> padded Z row
-  std::vector<int64_t> zoffp;    // first padded Z row of tile i
-  int64_t zp_tot = 0;
-  int64_t device_bytes = 0;
-  double setup_seconds[4] = {0, 0, 0, 0};  // tlr_factor phases
-  uint64_t checksum = 0;                   // FNV-1a of perm, diag, ranks, U, V
-  int64_t host_tiles = 0;                  // off-diagonal tiles compressed on the host
-};
 
 namespace tlrqmc {
 
+// The context stream is drained before the buffers go back: after the
+// synchronizations of the normal paths this costs nothing, and on an error
+// path it keeps a buffer from reaching its next user while a kernel queued
+// before the error still uses it.
 inline Scratch::~Scratch() {
+  if (!ptrs.empty()) (void)hipStreamSynchronize(ctx->stream);
   for (void *p : ptrs) ctx->dfree(p);
 }
 
@@ -227,64 +177,7 @@ int factor_build(tlrqmc_ctx *ctx, int64_t n, int m, const int32_t *perm, const d
                  const int32_t *ranks, const double *U, const double *V, int cap_hits,
                  tlrqmc_factor **out);
 
-// ---- kernels (kernels.hip) ----
-struct InitParams {
-  int64_t g0, count, N;
-  const uint64_t *A, *D;   // generators, shift table (ldD per shift)
-  int64_t ldD;
-  double nu;               // 0 = normal
-  double *logp;            // per chunk sample
-  double *R;               // per chunk sample (nu > 0)
-};
-
-struct SweepParams {
-  int64_t g0, count, N, ld, ldD;
-  int mj, c0;              // rows of the tile, lattice coordinate of row 0
-  const double *B;         // blocked tile
-  const double *a, *b;     // limits of the tile rows (a unused when one-sided)
-  const void *Delta;       // m x ld low-rank update (FP32 in the precision form, FP64 otherwise), or null
-  const double *R;         // per chunk sample, or null
-  const uint64_t *A, *D;
-  double *logp;            // per chunk sample
-  void *Y;                 // tile rows x ld: FP32 in the precision form, FP64 otherwise
-};
-
-struct LrParams {
-  int64_t count, ld;
-  int rows, K;             // delta: rows = m_i, K = krow; zproj: rows = K_col, K = m_j
-  int lda;                 // padded leading dimension of the tile operand
-  const double *Mat;       // U_row (col-major, lda rows) or V_panel (row-major, lda cols)
-  const double *In;        // Z rows (delta) or Y (zproj), ld-strided
-  double *Out;             // Delta (delta) or Z (zproj)
-  const int32_t *map;      // zproj: output row map
-};
-
-struct ReduceParams {
-  int64_t N;
-  int M;                   // shifts (blocks), read by the batched launch
-  const double *logp;
-  double *part;            // per shift: max, sum exp(lp - max), dead count
-};
-
-// C (rows x count) = A (rows x K) B (K x count) on BF16 matrix cores.  A is
-// pre-split into BF16 hi/lo, row-major with leading dimension KP (a
-// multiple of 32), rows padded to lr_mfma_rows(rows); B is FP32 or FP64
-// with leading dimension ld.  Output row c goes to row map[c] when a map
-// is given.
-struct MfmaLrParams {
-  int64_t count, ld;
-  int rows, K, KP;
-  const unsigned short *Ahi, *Alo;
-  const float *Bf;         // B in FP32, or null
-  const double *Bd;        // B in FP64, or null
-  const int32_t *map;      // output row map, or null
-  float *Out;
-};
-
-int lr_mfma_rt(int rows);
-int64_t lr_mfma_rows(int rows);
-// Work-groups of one launch of lr_mfma over count samples and rows rows.
-int64_t lr_mfma_blocks(int64_t count, int rows);
+// ---- kernels (kernels.hip, kernels_lr64.hip, kernels_mfma.hip) ----
 void launch_lr_mfma(hipStream_t s, const MfmaLrParams &p);
 void launch_init(hipStream_t s, const InitParams &p);
 void launch_sweep(hipStream_t s, const SweepParams &p, bool two_sided, bool scaled, bool prec);

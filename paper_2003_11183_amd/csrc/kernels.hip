@@ -364,10 +364,10 @@ __global__ __launch_bounds__(256) void k_reduce_batch(const ReduceParams *ps) {
 }
 
 // ------------------------------------------------------------ launchers ----
-static inline unsigned grid_of(int64_t count) { return static_cast<unsigned>((count + 255) / 256); }
+static inline dim3 dim3_of(const Grid &g) { return dim3(g.x, g.y, g.z); }
 
 void launch_init(hipStream_t s, const InitParams &p) {
-  hipLaunchKernelGGL(k_init, dim3(grid_of(p.count)), dim3(256), 0, s, p);
+  hipLaunchKernelGGL(k_init, dim3_of(init_grid(p.count)), dim3(256), 0, s, p);
 }
 
 template <bool TWO_SIDED, bool SCALED>
@@ -377,7 +377,7 @@ static void sweep_form(hipStream_t s, const SweepParams &p, dim3 grid, bool prec
 }
 
 void launch_sweep(hipStream_t s, const SweepParams &p, bool two_sided, bool scaled, bool prec) {
-  const dim3 grid(grid_of(p.count));
+  const dim3 grid = dim3_of(sweep_grid(p.count));
   if (two_sided) {
     if (scaled) sweep_form<true, true>(s, p, grid, prec);
     else sweep_form<true, false>(s, p, grid, prec);
@@ -388,16 +388,15 @@ void launch_sweep(hipStream_t s, const SweepParams &p, bool two_sided, bool scal
 }
 
 void launch_zproj_f64(hipStream_t s, const LrParams &p) {
-  const dim3 grid(grid_of(p.count), static_cast<unsigned>((p.rows + kLrRows - 1) / kLrRows));
-  hipLaunchKernelGGL(k_zproj_f64, grid, dim3(256), 0, s, p);
+  hipLaunchKernelGGL(k_zproj_f64, dim3_of(zproj_f64_grid(p.count, p.rows)), dim3(256), 0, s, p);
 }
 
 void launch_reduce(hipStream_t s, const ReduceParams &p, int n_shifts) {
-  hipLaunchKernelGGL(k_reduce, dim3(n_shifts), dim3(256), 0, s, p);
+  hipLaunchKernelGGL(k_reduce, dim3_of(reduce_grid(n_shifts)), dim3(256), 0, s, p);
 }
 
 void launch_init_batch(hipStream_t s, const InitParams *d, int n, int64_t max_count) {
-  hipLaunchKernelGGL(k_init_batch, dim3(grid_of(max_count), n), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(k_init_batch, dim3_of(init_batch_grid(n, max_count)), dim3(256), 0, s, d);
 }
 
 template <bool TWO_SIDED, bool SCALED>
@@ -408,7 +407,7 @@ static void sweep_batch_form(hipStream_t s, const SweepParams *d, dim3 grid, boo
 
 void launch_sweep_batch(hipStream_t s, const SweepParams *d, int n, int64_t max_count, bool two_sided, bool scaled,
                         bool prec) {
-  const dim3 grid(grid_of(max_count), n);
+  const dim3 grid = dim3_of(sweep_batch_grid(n, max_count));
   if (two_sided) {
     if (scaled) sweep_batch_form<true, true>(s, d, grid, prec);
     else sweep_batch_form<true, false>(s, d, grid, prec);
@@ -419,12 +418,11 @@ void launch_sweep_batch(hipStream_t s, const SweepParams *d, int n, int64_t max_
 }
 
 void launch_zproj_f64_batch(hipStream_t s, const LrParams *d, int n, int64_t max_count, int max_rows) {
-  const dim3 grid(grid_of(max_count), static_cast<unsigned>((max_rows + kLrRows - 1) / kLrRows), n);
-  hipLaunchKernelGGL(k_zproj_f64_batch, grid, dim3(256), 0, s, d);
+  hipLaunchKernelGGL(k_zproj_f64_batch, dim3_of(zproj_f64_batch_grid(n, max_count, max_rows)), dim3(256), 0, s, d);
 }
 
 void launch_reduce_batch(hipStream_t s, const ReduceParams *d, int n, int max_shifts) {
-  hipLaunchKernelGGL(k_reduce_batch, dim3(max_shifts, n), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(k_reduce_batch, dim3_of(reduce_batch_grid(n, max_shifts)), dim3(256), 0, s, d);
 }
 
 }  // namespace tlrqmc

@@ -29,7 +29,7 @@ namespace {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-constexpr int KC = 16, TR = 128, LP = TR + 4;
+constexpr int KC = 16, TR = kLr64Tile, LP = TR + 4;
 
 __device__ __forceinline__ void lr64_body(const LrParams &p, int rb, int64_t sb) {
   __shared__ double As[2][KC][LP], Bs[2][KC][LP];
@@ -124,20 +124,19 @@ __global__ __launch_bounds__(256) void k_lr64_batch(const LrParams *ps) {
   lr64_body(p, static_cast<int>(blockIdx.y), blockIdx.x);
 }
 
-dim3 lr64_grid(int64_t count, int rows, int n) {
-  return dim3(static_cast<unsigned>((count + TR - 1) / TR), static_cast<unsigned>((rows + TR - 1) / TR), n);
-}
 
 }  // namespace
 
 void launch_delta_f64(hipStream_t s, const LrParams &p) {
   if (p.count <= 0 || p.rows <= 0) return;
-  hipLaunchKernelGGL(k_lr64, lr64_grid(p.count, p.rows, 1), dim3(256), 0, s, p);
+  const Grid g = lr64_grid(p.count, p.rows, 1);
+  hipLaunchKernelGGL(k_lr64, dim3(g.x, g.y, g.z), dim3(256), 0, s, p);
 }
 
 void launch_delta_f64_batch(hipStream_t s, const LrParams *d, int n, int64_t max_count, int max_rows) {
   if (n <= 0 || max_count <= 0 || max_rows <= 0) return;
-  hipLaunchKernelGGL(k_lr64_batch, lr64_grid(max_count, max_rows, n), dim3(256), 0, s, d);
+  const Grid g = lr64_batch_grid(n, max_count, max_rows);
+  hipLaunchKernelGGL(k_lr64_batch, dim3(g.x, g.y, g.z), dim3(256), 0, s, d);
 }
 
 }  // namespace tlrqmc

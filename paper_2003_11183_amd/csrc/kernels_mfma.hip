@@ -212,17 +212,7 @@ __global__ __launch_bounds__(256) void k_lr_mfma_batch(const MfmaLrParams *ps) {
   lr_mfma_body<RT, NT, BD, MAP>(p, blockIdx.x, total);
 }
 
-// Row tiles of 16 per wave: one for operands of at most 64 rows, else two
-// (measured at n = 16,384 against four, with 64-, 128- and 256-sample
-// blocks: 128 samples and two row tiles were fastest for both products).
-int lr_mfma_rt(int rows) { return rows <= 64 ? 1 : 2; }
-
-int64_t lr_mfma_rows(int rows) { return round_up(rows > 0 ? rows : 1, 64 * lr_mfma_rt(rows)); }
-
 namespace {
-
-// Sample tiles of 16 per work-group (128 samples).
-constexpr int kLrNT = 8;
 
 template <int RT>
 void launch_rt(hipStream_t s, const MfmaLrParams &p, dim3 grid) {
@@ -250,9 +240,7 @@ void launch_batch_rt(hipStream_t s, const MfmaLrParams *d, dim3 grid, bool bd, b
 
 void launch_lr_mfma(hipStream_t s, const MfmaLrParams &p) {
   const int rt = lr_mfma_rt(p.rows);
-  const int64_t nsb = (p.count + 16 * kLrNT - 1) / (16 * kLrNT);
-  const int nrb = (p.rows + 64 * rt - 1) / (64 * rt);
-  const dim3 grid(static_cast<unsigned>(nsb * nrb));
+  const dim3 grid(lr_mfma_grid(p.count, p.rows).x);
   if (rt == 1) launch_rt<1>(s, p, grid);
   else launch_rt<2>(s, p, grid);
 }
@@ -262,14 +250,10 @@ void launch_lr_mfma(hipStream_t s, const MfmaLrParams &p) {
 // (lr_mfma_blocks).
 void launch_lr_mfma_batch(hipStream_t s, const MfmaLrParams *d, int n, int rt, bool fp64_b, bool map,
                           int64_t max_blocks) {
-  const dim3 grid(static_cast<unsigned>(round_up(max_blocks, 8)), static_cast<unsigned>(n));
+  const Grid g = lr_mfma_batch_grid(n, max_blocks);
+  const dim3 grid(g.x, g.y, g.z);
   if (rt == 1) launch_batch_rt<1>(s, d, grid, fp64_b, map);
   else launch_batch_rt<2>(s, d, grid, fp64_b, map);
-}
-
-int64_t lr_mfma_blocks(int64_t count, int rows) {
-  const int rt = lr_mfma_rt(rows);
-  return (count + 16 * kLrNT - 1) / (16 * kLrNT) * ((rows + 64 * rt - 1) / (64 * rt));
 }
 
 }  // namespace tlrqmc

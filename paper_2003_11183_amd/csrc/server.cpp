@@ -37,10 +37,6 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-// Samples per slot at most, and the device bytes one slot's buffers may
-// take; a request's slots all have the same size.
-constexpr int64_t kSlotSamples = 32768;
-constexpr int64_t kSlotBytes = int64_t{2} << 30;
 // Active slots per step (descriptor capacity of one step).
 constexpr int kMaxSlots = 64;
 // Requests set up concurrently: one's device work (Cholesky, compression)
@@ -160,17 +156,15 @@ struct Slot {
   Request *q = nullptr;
   int64_t c0 = 0, cnt = 0;
   int j = 0;
-  void *Y = nullptr;  // FP32 in the precision form
-  double *Dl = nullptr, *Z = nullptr, *R = nullptr;
-  float *DlF = nullptr, *ZF = nullptr;
+  ChunkBuffers b;
 };
 
 // Descriptors of one step, grouped by kernel variant.
 struct StepBatch {
   std::vector<InitParams> init;
   int64_t init_max = 0;
-  std::vector<MfmaLrParams> lr[2][3];  // [delta, projection][rt 1, 2, 4]
-  int64_t lr_max[2][3] = {};
+  std::vector<MfmaLrParams> lr[2][2];  // [delta, projection][row tiles 1, 2]
+  int64_t lr_max[2][2] = {};
   std::vector<LrParams> f64[2];        // [delta, projection]
   int64_t f64_max[2] = {};
   int f64_rows[2] = {};
@@ -194,7 +188,7 @@ struct StepBatch {
   }
 };
 
-int rt_index(int rt) { return rt == 1 ? 0 : rt == 2 ? 1 : 2; }
+int rt_index(int rt) { return rt - 1; }
 
 }  // namespace
 }  // namespace tlrqmc
@@ -369,22 +363,11 @@ bool tlrqmc_server::plan(Request *q) {
   }
   const int64_t M = q->qmc.n_shifts, N = q->qmc.n_samples;
   q->count = N * M;
-  const int64_t mpad = round_up(f->m, 64);
-  const int r = f->r;
   auto al = [](int64_t b) { return round_up(b, kAlign); };
-  auto slot_bytes = [&](int64_t ld) {
-    int64_t b = al((q->prec ? 4 : 8) * mpad * ld);
-    if (r > 1) b += al((q->prec ? 4 : 8) * mpad * ld);
-    if (f->k_tot > 0) b += al(q->prec ? 4 * f->zp_tot * ld : 8 * f->k_tot * ld);
-    if (q->scaled) b += al(8 * ld);
-    return b;
-  };
-  const int64_t per_sample = slot_bytes(256) / 256 + 1;
-  const int64_t chunk = std::min<int64_t>({q->count, kSlotSamples, std::max<int64_t>(256, kSlotBytes / per_sample)});
-  int nslots = static_cast<int>((q->count + chunk - 1) / chunk);
-  q->chunk = round_up((q->count + nslots - 1) / nslots, 256);
-  q->nslots = static_cast<int>((q->count + q->chunk - 1) / q->chunk);
-  q->slot_bytes = slot_bytes(q->chunk);
+  const SlotPlan sp = plan_slots(f, q->prec, q->scaled, q->count);
+  q->chunk = sp.chunk;
+  q->nslots = sp.nslots;
+  q->slot_bytes = sp.slot_bytes;
   q->req_bytes = al(8 * q->n) * (q->two_sided ? 2 : 1) + al(8 * M * (q->n + 1)) + al(8 * q->count) + al(8 * 3 * M);
   const int64_t fixed = f->device_bytes + q->req_bytes;
   const int64_t f_min = fixed + q->slot_bytes, f_all = fixed + q->nslots * q->slot_bytes;
@@ -452,24 +435,21 @@ bool tlrqmc_server::activate_slot(Request *q) {
   s.q = q;
   s.c0 = static_cast<int64_t>(q->started) * q->chunk;
   s.cnt = std::min(q->chunk, q->count - s.c0);
-  const int64_t ld = q->chunk, mpad = round_up(q->f->m, 64);
-  const tlrqmc_factor *f = q->f;
   std::vector<void *> got;
-  auto take = [&](int64_t bytes) {
-    void *p = arena.alloc(bytes);
-    got.push_back(p);
-    return p;
-  };
-  s.Y = take((q->prec ? 4 : 8) * mpad * ld);
-  if (f->r > 1) {
-    if (q->prec) s.DlF = static_cast<float *>(take(4 * mpad * ld));
-    else s.Dl = static_cast<double *>(take(8 * mpad * ld));
+  int64_t bytes[4];
+  chunk_buffer_bytes(q->f, q->prec, q->scaled, q->chunk, bytes);
+  void *b[4] = {nullptr, nullptr, nullptr, nullptr};
+  for (int k = 0; k < 4; ++k)
+    if (bytes[k] > 0) got.push_back(b[k] = arena.alloc(bytes[k]));
+  s.b.Y = b[0];
+  s.b.R = static_cast<double *>(b[3]);
+  if (q->prec) {
+    s.b.DlF = static_cast<float *>(b[1]);
+    s.b.ZF = static_cast<float *>(b[2]);
+  } else {
+    s.b.Dl = static_cast<double *>(b[1]);
+    s.b.Z = static_cast<double *>(b[2]);
   }
-  if (f->k_tot > 0) {
-    if (q->prec) s.ZF = static_cast<float *>(take(4 * f->zp_tot * ld));
-    else s.Z = static_cast<double *>(take(8 * f->k_tot * ld));
-  }
-  if (q->scaled) s.R = static_cast<double *>(take(8 * ld));
   for (void *p : got)
     if (!p) {
       for (void *x : got) arena.free(x);
@@ -517,53 +497,36 @@ int tlrqmc_server::step(StepBatch &B, int cur) {
     Request *q = s.q;
     const tlrqmc_factor *f = q->f;
     const int j = s.j, r = f->r;
-    const int64_t ld = q->chunk, n = q->n, N = q->qmc.n_samples;
+    const int64_t ld = q->chunk, N = q->qmc.n_samples;
+    const ChunkRun run{s.c0, s.cnt, N, ld, q->prec, s.b, q->d_a, q->d_b, q->d_D, q->d_logp + s.c0};
     if (j == 0) {
-      B.init.push_back(InitParams{s.c0, s.cnt, N, f->d_gen, q->d_D, n + 1, q->nu, q->d_logp + s.c0, s.R});
+      B.init.push_back(init_launch(f, run, q->nu));
       B.init_max = std::max(B.init_max, s.cnt);
     }
-    const bool has_delta = j > 0 && f->krow[j] > 0;
-    if (has_delta) {
+    const TileLaunch t = tile_launch(f, j, run);
+    if (t.delta) {
       if (q->prec) {
-        const unsigned short *u = f->d_ubf + f->ubf_off[j];
-        const int rt = lr_mfma_rt(f->tm[j]);
-        B.lr[0][rt_index(rt)].push_back(MfmaLrParams{s.cnt, ld, f->tm[j], static_cast<int>(f->krow[j]), f->kp_row[j], u,
-                                                     u + f->ubf_size[j], s.ZF + f->zoffp[j] * ld, nullptr, nullptr,
-                                                     s.DlF});
-        const int64_t blocks = lr_mfma_blocks(s.cnt, f->tm[j]);
-        B.lr_max[0][rt_index(rt)] = std::max(B.lr_max[0][rt_index(rt)], blocks);
+        const int k = rt_index(lr_mfma_rt(t.delta_mfma.rows));
+        B.lr[0][k].push_back(t.delta_mfma);
+        B.lr_max[0][k] = std::max(B.lr_max[0][k], lr_mfma_blocks(s.cnt, t.delta_mfma.rows));
       } else {
-        B.f64[0].push_back(LrParams{s.cnt, ld, f->tm[j], static_cast<int>(f->krow[j]), f->urow_ld[j],
-                                    f->d_urow + f->urow_off[j], s.Z + f->zoff[j] * ld, s.Dl, nullptr});
+        B.f64[0].push_back(t.delta_f64);
         B.f64_max[0] = std::max(B.f64_max[0], s.cnt);
-        B.f64_rows[0] = std::max(B.f64_rows[0], f->tm[j]);
+        B.f64_rows[0] = std::max(B.f64_rows[0], t.delta_f64.rows);
       }
     }
     const int v = (q->two_sided ? 4 : 0) + (q->scaled ? 2 : 0) + (q->prec ? 1 : 0);
-    B.sweep[v].push_back(SweepParams{s.c0, s.cnt, N, ld, n + 1, f->tm[j], static_cast<int>(1 + f->toff[j]),
-                                     f->d_diag + f->diag_off[j], q->two_sided ? q->d_a + f->toff[j] : nullptr,
-                                     q->d_b + f->toff[j],
-                                     has_delta ? (q->prec ? static_cast<const void *>(s.DlF)
-                                                          : static_cast<const void *>(s.Dl))
-                                               : nullptr,
-                                     s.R, f->d_gen, q->d_D, q->d_logp + s.c0, s.Y});
+    B.sweep[v].push_back(t.sweep);
     B.sweep_max[v] = std::max(B.sweep_max[v], s.cnt);
-    if (j < r - 1 && f->kcol[j] > 0) {
+    if (t.zproj) {
       if (q->prec) {
-        const unsigned short *vv = f->d_vbf + f->vbf_off[j];
-        const int rows = static_cast<int>(f->kcol[j]);
-        const int rt = lr_mfma_rt(rows);
-        B.lr[1][rt_index(rt)].push_back(MfmaLrParams{s.cnt, ld, rows, f->tm[j], f->vbf_mp[j], vv, vv + f->vbf_size[j],
-                                                     static_cast<const float *>(s.Y), nullptr,
-                                                     f->d_zmapp + f->zmap_off[j], s.ZF});
-        const int64_t blocks = lr_mfma_blocks(s.cnt, rows);
-        B.lr_max[1][rt_index(rt)] = std::max(B.lr_max[1][rt_index(rt)], blocks);
+        const int k = rt_index(lr_mfma_rt(t.zproj_mfma.rows));
+        B.lr[1][k].push_back(t.zproj_mfma);
+        B.lr_max[1][k] = std::max(B.lr_max[1][k], lr_mfma_blocks(s.cnt, t.zproj_mfma.rows));
       } else {
-        B.f64[1].push_back(LrParams{s.cnt, ld, static_cast<int>(f->kcol[j]), f->tm[j], f->vpan_ld[j],
-                                    f->d_vpan + f->vpan_off[j], static_cast<const double *>(s.Y), s.Z,
-                                    f->d_zmap + f->zmap_off[j]});
+        B.f64[1].push_back(t.zproj_f64);
         B.f64_max[1] = std::max(B.f64_max[1], s.cnt);
-        B.f64_rows[1] = std::max(B.f64_rows[1], static_cast<int>(f->kcol[j]));
+        B.f64_rows[1] = std::max(B.f64_rows[1], t.zproj_f64.rows);
       }
     }
     ++slot_steps;
@@ -572,8 +535,8 @@ int tlrqmc_server::step(StepBatch &B, int cur) {
       continue;
     }
     // slot finished: its buffers are free once this step has run
-    for (void *p : {static_cast<void *>(s.Y), static_cast<void *>(s.Dl), static_cast<void *>(s.Z),
-                    static_cast<void *>(s.R), static_cast<void *>(s.DlF), static_cast<void *>(s.ZF)})
+    for (void *p : {s.b.Y, static_cast<void *>(s.b.Dl), static_cast<void *>(s.b.Z), static_cast<void *>(s.b.R),
+                    static_cast<void *>(s.b.DlF), static_cast<void *>(s.b.ZF)})
       if (p) defer_free[cur].push_back(p);
     --q->active;
     if (++q->finished == q->nslots) {
@@ -593,9 +556,9 @@ int tlrqmc_server::step(StepBatch &B, int cur) {
     return at;
   };
   const size_t o_init = stage(B.init.data(), B.init.size() * sizeof(InitParams));
-  size_t o_lr[2][3], o_f64[2], o_sw[8];
+  size_t o_lr[2][2], o_f64[2], o_sw[8];
   for (int k = 0; k < 2; ++k)
-    for (int t = 0; t < 3; ++t) o_lr[k][t] = stage(B.lr[k][t].data(), B.lr[k][t].size() * sizeof(MfmaLrParams));
+    for (int t = 0; t < 2; ++t) o_lr[k][t] = stage(B.lr[k][t].data(), B.lr[k][t].size() * sizeof(MfmaLrParams));
   for (int k = 0; k < 2; ++k) o_f64[k] = stage(B.f64[k].data(), B.f64[k].size() * sizeof(LrParams));
   for (int v = 0; v < 8; ++v) o_sw[v] = stage(B.sweep[v].data(), B.sweep[v].size() * sizeof(SweepParams));
   const size_t o_red = stage(B.reduce.data(), B.reduce.size() * sizeof(ReduceParams));
@@ -610,11 +573,10 @@ int tlrqmc_server::step(StepBatch &B, int cur) {
     launch_init_batch(st, reinterpret_cast<const InitParams *>(d + o_init), static_cast<int>(B.init.size()), B.init_max);
     ++nl;
   }
-  static const int kRt[3] = {1, 2, 4};
-  for (int t = 0; t < 3; ++t)
+  for (int t = 0; t < 2; ++t)
     if (!B.lr[0][t].empty()) {
       launch_lr_mfma_batch(st, reinterpret_cast<const MfmaLrParams *>(d + o_lr[0][t]),
-                           static_cast<int>(B.lr[0][t].size()), kRt[t], false, false, B.lr_max[0][t]);
+                           static_cast<int>(B.lr[0][t].size()), t + 1, false, false, B.lr_max[0][t]);
       ++nl;
     }
   if (!B.f64[0].empty()) {
@@ -628,10 +590,10 @@ int tlrqmc_server::step(StepBatch &B, int cur) {
                          B.sweep_max[v], (v & 4) != 0, (v & 2) != 0, (v & 1) != 0);
       ++nl;
     }
-  for (int t = 0; t < 3; ++t)
+  for (int t = 0; t < 2; ++t)
     if (!B.lr[1][t].empty()) {
       launch_lr_mfma_batch(st, reinterpret_cast<const MfmaLrParams *>(d + o_lr[1][t]),
-                           static_cast<int>(B.lr[1][t].size()), kRt[t], false, true, B.lr_max[1][t]);
+                           static_cast<int>(B.lr[1][t].size()), t + 1, false, true, B.lr_max[1][t]);
       ++nl;
     }
   if (!B.f64[1].empty()) {

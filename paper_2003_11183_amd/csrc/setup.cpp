@@ -945,10 +945,16 @@ int factor_from_device_dense(tlrqmc_ctx *ctx, int64_t n, const double *S, int64_
   double *A = static_cast<double *>(ctx->dmalloc(static_cast<size_t>(lda) * n * sizeof(double)));
   if (!A) return fail(TLRQMC_ENOMEM, "device allocation of the %lld x %lld covariance failed",
                       static_cast<long long>(n), static_cast<long long>(n));
-  std::unique_ptr<double, std::function<void(double *)>> Aguard(A, [ctx](double *q) { ctx->dfree(q); });
+  std::unique_ptr<double, std::function<void(double *)>> Aguard(A, [ctx](double *q) {
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->dfree(q);
+  });
   int32_t *dp = static_cast<int32_t *>(ctx->dmalloc(n * sizeof(int32_t)));
   if (!dp) return fail(TLRQMC_ENOMEM, "device allocation failed");
-  std::unique_ptr<int32_t, std::function<void(int32_t *)>> pguard(dp, [ctx](int32_t *q) { ctx->dfree(q); });
+  std::unique_ptr<int32_t, std::function<void(int32_t *)>> pguard(dp, [ctx](int32_t *q) {
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->dfree(q);
+  });
   if (hipMemcpyAsync(dp, p.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess)
     return fail(TLRQMC_EDEVICE, "copy of the order failed");
   {
@@ -1054,7 +1060,10 @@ int tlr_factor(tlrqmc_ctx *ctx, int64_t n, const tlrqmc_cov *cov, const int32_t 
   double *A = static_cast<double *>(ctx->dmalloc(static_cast<size_t>(lda) * n * sizeof(double)));
   if (!A) return fail(TLRQMC_ENOMEM, "device allocation of the %lld x %lld covariance failed",
                       static_cast<long long>(n), static_cast<long long>(n));
-  std::unique_ptr<double, std::function<void(double *)>> Aguard(A, [ctx](double *q) { ctx->dfree(q); });
+  std::unique_ptr<double, std::function<void(double *)>> Aguard(A, [ctx](double *q) {
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->dfree(q);
+  });
   if ((st = build_cov(ctx, n, cov, p, A, lda))) return st;
   rocblas_handle h = blas_of(ctx);
   if (!h) return fail(TLRQMC_EDEVICE, "rocblas_create_handle failed");
@@ -1085,7 +1094,10 @@ int tlr_factor_rbodr(tlrqmc_ctx *ctx, int64_t n, const tlrqmc_cov *cov, const do
   double *A = static_cast<double *>(ctx->dmalloc(static_cast<size_t>(lda) * n * sizeof(double)));
   if (!A) return fail(TLRQMC_ENOMEM, "device allocation of the %lld x %lld covariance failed",
                       static_cast<long long>(n), static_cast<long long>(n));
-  std::unique_ptr<double, std::function<void(double *)>> Aguard(A, [ctx](double *q) { ctx->dfree(q); });
+  std::unique_ptr<double, std::function<void(double *)>> Aguard(A, [ctx](double *q) {
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->dfree(q);
+  });
   if ((st = build_cov(ctx, n, cov, p, A, lda))) return st;
   rocblas_handle h = blas_of(ctx);
   if (!h) return fail(TLRQMC_EDEVICE, "rocblas_create_handle failed");
