@@ -30,11 +30,14 @@
  *  - Concurrent device linear algebra: rocBLAS / rocSOLVER factorizations
  *    (and torch.linalg.cholesky) returned wrong results while this
  *    library's estimator kernels ran beside them on other streams; the cause
- *    has not been found (an audit of this library's device accesses found
- *    no access outside its buffers).  Every rocBLAS call the library makes
- *    itself runs with the device drained and to itself.  Callers should not
- *    run their own device factorizations concurrently with mvn_prob,
- *    mvt_prob or a server of this library: synchronize first.
+ *    has not been found.  A host replay of every load and store of the
+ *    estimator kernels, over the launches the library builds for full-size
+ *    problems, served slots and small ragged ones, finds none outside its
+ *    allocation, and no buffer goes back to the allocator while a kernel
+ *    may still use it.  Every rocBLAS call the library makes itself runs
+ *    with the device drained and to itself.  Callers should not run their
+ *    own device factorizations concurrently with mvn_prob, mvt_prob or a
+ *    server of this library: synchronize first.
  */
 #ifndef TLRQMC_H
 #define TLRQMC_H
