@@ -305,21 +305,32 @@ __global__ __launch_bounds__(256) void k_zproj_f64_batch(const LrParams *ps) {
 
 // -------------------------------------------------------------- reduce ----
 // One block per shift: max of log P, then sum of exp(log P - max) and the
-// count of empty samples, each lane striding in a fixed order and the lanes
-// combined by a fixed tree, so the result does not depend on scheduling.
-__device__ __forceinline__ void reduce_body(const ReduceParams &p, int s, double *sh, double *sd) {
-  const int t = threadIdx.x;
+// count of empty samples.  Each lane strides over the samples in a fixed
+// order; a wave combines its lanes by a butterfly of lane exchanges (lane i
+// and lane i ^ d add the same two values, so every lane ends with the same
+// sum), and the four waves' results are combined in a fixed order, so the
+// result does not depend on scheduling.
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v = fmax(v, __shfl_xor(v, d, 64));
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+__device__ __forceinline__ void reduce_body(const ReduceParams &p, int s, double *sh) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const double *lp = p.logp + static_cast<int64_t>(s) * p.N;
   double mx = -INFINITY;
   for (int64_t i = t; i < p.N; i += 256) mx = fmax(mx, lp[i]);
-  sh[t] = mx;
+  mx = wave_max(mx);
+  if (lane == 0) sh[w] = mx;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w) sh[t] = fmax(sh[t], sh[t + w]);
-    __syncthreads();
-  }
-  mx = sh[0];
-  __syncthreads();
+  mx = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
   double sum = 0.0, dead = 0.0;
   if (mx > -INFINITY) {
     for (int64_t i = t; i < p.N; i += 256) {
@@ -330,37 +341,32 @@ __device__ __forceinline__ void reduce_body(const ReduceParams &p, int s, double
   } else {
     for (int64_t i = t; i < p.N; i += 256) dead += 1.0;
   }
-  sh[t] = sum;
-  sd[t] = dead;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w) {
-      sh[t] += sh[t + w];
-      sd[t] += sd[t + w];
-    }
-    __syncthreads();
+  sum = wave_sum(sum);
+  dead = wave_sum(dead);
+  if (lane == 0) {
+    sh[4 + w] = sum;
+    sh[8 + w] = dead;
   }
+  __syncthreads();
   if (t == 0) {
     p.part[3 * s + 0] = mx;
-    p.part[3 * s + 1] = sh[0];
-    p.part[3 * s + 2] = sd[0];
+    p.part[3 * s + 1] = (sh[4] + sh[5]) + (sh[6] + sh[7]);
+    p.part[3 * s + 2] = (sh[8] + sh[9]) + (sh[10] + sh[11]);
   }
 }
 
 __global__ __launch_bounds__(256) void k_reduce(ReduceParams p) {
-  __shared__ double sh[256];
-  __shared__ double sd[256];
-  reduce_body(p, blockIdx.x, sh, sd);
+  __shared__ double sh[12];
+  reduce_body(p, blockIdx.x, sh);
 }
 
 // One block per (shift, request); blocks past a request's shift count
 // leave at once (the whole block takes the same branch).
 __global__ __launch_bounds__(256) void k_reduce_batch(const ReduceParams *ps) {
-  __shared__ double sh[256];
-  __shared__ double sd[256];
+  __shared__ double sh[12];
   const ReduceParams p = load_uniform(ps + blockIdx.y);
   if (static_cast<int>(blockIdx.x) >= p.M) return;
-  reduce_body(p, blockIdx.x, sh, sd);
+  reduce_body(p, blockIdx.x, sh);
 }
 
 // ------------------------------------------------------------ launchers ----
