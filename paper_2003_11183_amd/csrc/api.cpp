@@ -77,32 +77,42 @@ void estimate_from_parts(const std::vector<double> &part, int M, int64_t N, tlrq
 namespace {
 
 
-// HIP events around launches (on the launch's own stream), summed per
-// kernel kind.
+// Start and stop events of every launch (marked by the launch itself),
+// summed per kernel kind.  The events come from the context's pool and go
+// back to it.
 struct Profiler {
   bool on;
+  tlrqmc_ctx *ctx;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
-  int open_kind = -1;
-  hipEvent_t open_ev = nullptr;
-  explicit Profiler(bool enable) : on(enable) {}
+  Profiler(bool enable, tlrqmc_ctx *c) : on(enable), ctx(c) {}
   ~Profiler() {
     for (auto &m : marks) {
-      (void)hipEventDestroy(m.second.first);
-      (void)hipEventDestroy(m.second.second);
+      ctx->event_pool.push_back(m.second.first);
+      ctx->event_pool.push_back(m.second.second);
     }
   }
-  void begin(int kind, hipStream_t s) {
-    if (!on) return;
-    (void)hipEventCreate(&open_ev);
-    (void)hipEventRecord(open_ev, s);
-    open_kind = kind;
+  hipEvent_t take() {
+    hipEvent_t e = nullptr;
+    if (!ctx->event_pool.empty()) {
+      e = ctx->event_pool.back();
+      ctx->event_pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+    }
+    return e;
   }
-  void end(hipStream_t s) {
-    if (!on) return;
-    hipEvent_t e;
-    (void)hipEventCreate(&e);
-    (void)hipEventRecord(e, s);
-    marks.push_back({open_kind, {open_ev, e}});
+  // the events of the next launch of this kind (none when profiling is off)
+  LaunchEvents next(int kind) {
+    LaunchEvents ev;
+    if (!on) return ev;
+    ev.start = take();
+    ev.stop = ev.start ? take() : nullptr;
+    if (!ev.stop) {
+      if (ev.start) ctx->event_pool.push_back(ev.start);
+      return LaunchEvents{};
+    }
+    marks.push_back({kind, {ev.start, ev.stop}});
+    return ev;
   }
   // Sum of launch durations and, per kind, the union of the launch
   // intervals (launches on different streams may overlap), both measured
@@ -290,7 +300,7 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
     if (!ev0 || !ev1 || !ev_in) return fail(TLRQMC_EDEVICE, "hipEventCreate failed");
   }
   const auto t_host0 = std::chrono::steady_clock::now();
-  Profiler prof(!fixed && opts->profile != 0);
+  Profiler prof(!fixed && opts->profile != 0, ctx);
   if (ev0) (void)hipEventRecord(ev0, st);
   if (ev_in) (void)hipEventRecord(ev_in, st);
   if (nstream > 1)
@@ -310,9 +320,7 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
                               d_logp + cs[w].first});
     for (size_t w = 0; w < cs.size(); ++w) {
       const Lane &L = lanes[w];
-      prof.begin(TLRQMC_KERNEL_INIT, L.s);
-      launch_init(L.s, init_launch(f, runs[w], nu));
-      prof.end(L.s);
+      launch_init(L.s, init_launch(f, runs[w], nu), prof.next(TLRQMC_KERNEL_INIT));
       if (!check_launch("init")) return fail_device(ctx, lanes.size());
     }
     for (int j = 0; j < r; ++j) {
@@ -320,21 +328,15 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
         const Lane &L = lanes[w];
         const TileLaunch t = tile_launch(f, j, runs[w]);
         if (t.delta) {
-          prof.begin(TLRQMC_KERNEL_DELTA, L.s);
-          if (prec) launch_lr_mfma(L.s, t.delta_mfma);
-          else launch_delta_f64(L.s, t.delta_f64);
-          prof.end(L.s);
+          if (prec) launch_lr_mfma(L.s, t.delta_mfma, prof.next(TLRQMC_KERNEL_DELTA));
+          else launch_delta_f64(L.s, t.delta_f64, prof.next(TLRQMC_KERNEL_DELTA));
           if (!check_launch("delta")) return fail_device(ctx, lanes.size());
         }
-        prof.begin(TLRQMC_KERNEL_SWEEP, L.s);
-        launch_sweep(L.s, t.sweep, two_sided, nu > 0, prec);
-        prof.end(L.s);
+        launch_sweep(L.s, t.sweep, two_sided, nu > 0, prec, prof.next(TLRQMC_KERNEL_SWEEP));
         if (!check_launch("sweep")) return fail_device(ctx, lanes.size());
         if (t.zproj) {
-          prof.begin(TLRQMC_KERNEL_ZPROJ, L.s);
-          if (prec) launch_lr_mfma(L.s, t.zproj_mfma);
-          else launch_zproj_f64(L.s, t.zproj_f64);
-          prof.end(L.s);
+          if (prec) launch_lr_mfma(L.s, t.zproj_mfma, prof.next(TLRQMC_KERNEL_ZPROJ));
+          else launch_zproj_f64(L.s, t.zproj_f64, prof.next(TLRQMC_KERNEL_ZPROJ));
           if (!check_launch("zproj")) return fail_device(ctx, lanes.size());
         }
       }
@@ -350,9 +352,7 @@ int run_estimator(tlrqmc_ctx *ctx, const tlrqmc_factor *f, const double *a, cons
     }
   if (reduce) {
     ReduceParams rp{N, M, d_logp, d_part};
-    prof.begin(TLRQMC_KERNEL_REDUCE, st);
-    launch_reduce(st, rp, M);
-    prof.end(st);
+    launch_reduce(st, rp, M, prof.next(TLRQMC_KERNEL_REDUCE));
     if (!check_launch("reduce")) return fail_device(ctx, lanes.size());
   }
   if (ev1) (void)hipEventRecord(ev1, st);
@@ -460,6 +460,7 @@ void tlrqmc_ctx_destroy(tlrqmc_ctx *ctx) {
   }
   ctx->release_pinned();
   release_blas(ctx);
+  for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
   delete ctx;
 }
 

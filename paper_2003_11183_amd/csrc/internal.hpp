@@ -62,6 +62,9 @@ struct tlrqmc_ctx {
   std::vector<hipStream_t> workers;
   // Pinned host staging buffers (factor download), kept between calls.
   std::vector<std::pair<void *, size_t>> staging;
+  // Timing events of profiled calls, kept between calls (a profiled call
+  // takes two per launch).
+  std::vector<hipEvent_t> event_pool;
   void *blas = nullptr;  // rocblas_handle, created by the first factor build
   void *dmalloc(size_t bytes);
   void dfree(void *p);
@@ -178,12 +181,19 @@ int factor_build(tlrqmc_ctx *ctx, int64_t n, int m, const int32_t *perm, const d
                  tlrqmc_factor **out);
 
 // ---- kernels (kernels.hip, kernels_lr64.hip, kernels_mfma.hip) ----
-void launch_lr_mfma(hipStream_t s, const MfmaLrParams &p);
-void launch_init(hipStream_t s, const InitParams &p);
-void launch_sweep(hipStream_t s, const SweepParams &p, bool two_sided, bool scaled, bool prec);
-void launch_delta_f64(hipStream_t s, const LrParams &p);
-void launch_zproj_f64(hipStream_t s, const LrParams &p);
-void launch_reduce(hipStream_t s, const ReduceParams &p, int n_shifts);
+// Optional start and stop events of one launch: when given, the launch
+// itself marks them (hipExtLaunchKernel), with no separate marker packets
+// in the stream.
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+void launch_lr_mfma(hipStream_t s, const MfmaLrParams &p, const LaunchEvents &ev = {});
+void launch_init(hipStream_t s, const InitParams &p, const LaunchEvents &ev = {});
+void launch_sweep(hipStream_t s, const SweepParams &p, bool two_sided, bool scaled, bool prec,
+                  const LaunchEvents &ev = {});
+void launch_delta_f64(hipStream_t s, const LrParams &p, const LaunchEvents &ev = {});
+void launch_zproj_f64(hipStream_t s, const LrParams &p, const LaunchEvents &ev = {});
+void launch_reduce(hipStream_t s, const ReduceParams &p, int n_shifts, const LaunchEvents &ev = {});
 
 // Batched launches: d points to n descriptors in device memory; slot i's
 // launch is the one its descriptor would make alone.

@@ -14,6 +14,8 @@
 //   k_zproj_f64 : Z(:, j) = V_panel(j)^T Y_j    (rank-space image of y_j;
 //                 precision form in kernels_mfma.hip)
 // and k_reduce combines log P per shift (Section 2.1: mean over samples).
+#include <hip/hip_ext.h>
+
 #include <type_traits>
 
 #include "device_math.hpp"
@@ -372,33 +374,34 @@ __global__ __launch_bounds__(256) void k_reduce_batch(const ReduceParams *ps) {
 // ------------------------------------------------------------ launchers ----
 static inline dim3 dim3_of(const Grid &g) { return dim3(g.x, g.y, g.z); }
 
-void launch_init(hipStream_t s, const InitParams &p) {
-  hipLaunchKernelGGL(k_init, dim3_of(init_grid(p.count)), dim3(256), 0, s, p);
+void launch_init(hipStream_t s, const InitParams &p, const LaunchEvents &ev) {
+  hipExtLaunchKernelGGL(k_init, dim3_of(init_grid(p.count)), dim3(256), 0, s, ev.start, ev.stop, 0, p);
 }
 
 template <bool TWO_SIDED, bool SCALED>
-static void sweep_form(hipStream_t s, const SweepParams &p, dim3 grid, bool prec) {
-  if (prec) hipLaunchKernelGGL((k_sweep<TWO_SIDED, SCALED, true>), grid, dim3(256), 0, s, p);
-  else hipLaunchKernelGGL((k_sweep<TWO_SIDED, SCALED, false>), grid, dim3(256), 0, s, p);
+static void sweep_form(hipStream_t s, const SweepParams &p, dim3 grid, bool prec, const LaunchEvents &ev) {
+  if (prec) hipExtLaunchKernelGGL((k_sweep<TWO_SIDED, SCALED, true>), grid, dim3(256), 0, s, ev.start, ev.stop, 0, p);
+  else hipExtLaunchKernelGGL((k_sweep<TWO_SIDED, SCALED, false>), grid, dim3(256), 0, s, ev.start, ev.stop, 0, p);
 }
 
-void launch_sweep(hipStream_t s, const SweepParams &p, bool two_sided, bool scaled, bool prec) {
+void launch_sweep(hipStream_t s, const SweepParams &p, bool two_sided, bool scaled, bool prec,
+                  const LaunchEvents &ev) {
   const dim3 grid = dim3_of(sweep_grid(p.count));
   if (two_sided) {
-    if (scaled) sweep_form<true, true>(s, p, grid, prec);
-    else sweep_form<true, false>(s, p, grid, prec);
+    if (scaled) sweep_form<true, true>(s, p, grid, prec, ev);
+    else sweep_form<true, false>(s, p, grid, prec, ev);
   } else {
-    if (scaled) sweep_form<false, true>(s, p, grid, prec);
-    else sweep_form<false, false>(s, p, grid, prec);
+    if (scaled) sweep_form<false, true>(s, p, grid, prec, ev);
+    else sweep_form<false, false>(s, p, grid, prec, ev);
   }
 }
 
-void launch_zproj_f64(hipStream_t s, const LrParams &p) {
-  hipLaunchKernelGGL(k_zproj_f64, dim3_of(zproj_f64_grid(p.count, p.rows)), dim3(256), 0, s, p);
+void launch_zproj_f64(hipStream_t s, const LrParams &p, const LaunchEvents &ev) {
+  hipExtLaunchKernelGGL(k_zproj_f64, dim3_of(zproj_f64_grid(p.count, p.rows)), dim3(256), 0, s, ev.start, ev.stop, 0, p);
 }
 
-void launch_reduce(hipStream_t s, const ReduceParams &p, int n_shifts) {
-  hipLaunchKernelGGL(k_reduce, dim3_of(reduce_grid(n_shifts)), dim3(256), 0, s, p);
+void launch_reduce(hipStream_t s, const ReduceParams &p, int n_shifts, const LaunchEvents &ev) {
+  hipExtLaunchKernelGGL(k_reduce, dim3_of(reduce_grid(n_shifts)), dim3(256), 0, s, ev.start, ev.stop, 0, p);
 }
 
 void launch_init_batch(hipStream_t s, const InitParams *d, int n, int64_t max_count) {

@@ -18,6 +18,8 @@
 // of v_mfma_f64_16x16x4_f64 (A operand lane l = row l % 16, k l / 16; B
 // operand lane l = sample l % 16, k l / 16; result lane l holds rows
 // l / 16 + 4 r, sample l % 16).  All arithmetic is FP64.
+#include <hip/hip_ext.h>
+
 #include "device_math.hpp"
 #include "internal.hpp"
 
@@ -127,10 +129,10 @@ __global__ __launch_bounds__(256) void k_lr64_batch(const LrParams *ps) {
 
 }  // namespace
 
-void launch_delta_f64(hipStream_t s, const LrParams &p) {
+void launch_delta_f64(hipStream_t s, const LrParams &p, const LaunchEvents &ev) {
   if (p.count <= 0 || p.rows <= 0) return;
   const Grid g = lr64_grid(p.count, p.rows, 1);
-  hipLaunchKernelGGL(k_lr64, dim3(g.x, g.y, g.z), dim3(256), 0, s, p);
+  hipExtLaunchKernelGGL(k_lr64, dim3(g.x, g.y, g.z), dim3(256), 0, s, ev.start, ev.stop, 0, p);
 }
 
 void launch_delta_f64_batch(hipStream_t s, const LrParams *d, int n, int64_t max_count, int max_rows) {

@@ -15,6 +15,8 @@
 // Operand layout of v_mfma_f32_16x16x32_bf16 (checked on the device): lane
 // l holds A[l % 16][8 (l / 16) + e] and B[8 (l / 16) + e][l % 16], e = 0..7,
 // and receives C[4 (l / 16) + i][l % 16], i = 0..3.
+#include <hip/hip_ext.h>
+
 #include <type_traits>
 
 #include "device_math.hpp"
@@ -215,13 +217,13 @@ __global__ __launch_bounds__(256) void k_lr_mfma_batch(const MfmaLrParams *ps) {
 namespace {
 
 template <int RT>
-void launch_rt(hipStream_t s, const MfmaLrParams &p, dim3 grid) {
+void launch_rt(hipStream_t s, const MfmaLrParams &p, dim3 grid, const LaunchEvents &ev) {
   if (p.Bd) {
-    if (p.map) hipLaunchKernelGGL((k_lr_mfma<RT, kLrNT, true, true>), grid, dim3(256), 0, s, p);
-    else hipLaunchKernelGGL((k_lr_mfma<RT, kLrNT, true, false>), grid, dim3(256), 0, s, p);
+    if (p.map) hipExtLaunchKernelGGL((k_lr_mfma<RT, kLrNT, true, true>), grid, dim3(256), 0, s, ev.start, ev.stop, 0, p);
+    else hipExtLaunchKernelGGL((k_lr_mfma<RT, kLrNT, true, false>), grid, dim3(256), 0, s, ev.start, ev.stop, 0, p);
   } else {
-    if (p.map) hipLaunchKernelGGL((k_lr_mfma<RT, kLrNT, false, true>), grid, dim3(256), 0, s, p);
-    else hipLaunchKernelGGL((k_lr_mfma<RT, kLrNT, false, false>), grid, dim3(256), 0, s, p);
+    if (p.map) hipExtLaunchKernelGGL((k_lr_mfma<RT, kLrNT, false, true>), grid, dim3(256), 0, s, ev.start, ev.stop, 0, p);
+    else hipExtLaunchKernelGGL((k_lr_mfma<RT, kLrNT, false, false>), grid, dim3(256), 0, s, ev.start, ev.stop, 0, p);
   }
 }
 
@@ -238,11 +240,11 @@ void launch_batch_rt(hipStream_t s, const MfmaLrParams *d, dim3 grid, bool bd, b
 
 }  // namespace
 
-void launch_lr_mfma(hipStream_t s, const MfmaLrParams &p) {
+void launch_lr_mfma(hipStream_t s, const MfmaLrParams &p, const LaunchEvents &ev) {
   const int rt = lr_mfma_rt(p.rows);
   const dim3 grid(lr_mfma_grid(p.count, p.rows).x);
-  if (rt == 1) launch_rt<1>(s, p, grid);
-  else launch_rt<2>(s, p, grid);
+  if (rt == 1) launch_rt<1>(s, p, grid, ev);
+  else launch_rt<2>(s, p, grid, ev);
 }
 
 // Every descriptor of one batched launch must have lr_mfma_rt(rows) == rt
