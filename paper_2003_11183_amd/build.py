@@ -32,10 +32,13 @@ DEVICE = [os.path.join(ROCM, "bin", "hipcc"), f"--offload-arch={ARCH}",
           "-mllvm", "-disable-machine-licm"] + COMMON
 
 
-# Per-file device options.  The low-rank MFMA kernels keep their
-# accumulators in ordinary VGPRs instead of AGPRs: the two share one register
-# file, and the VGPR form needs fewer registers in total (more waves).
-FILE_FLAGS = {"kernels_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+# Per-file device options.  The low-rank MFMA kernels and the sweep keep
+# their matrix-core accumulators in ordinary VGPRs instead of AGPRs: the two
+# share one register file, and the VGPR form needs fewer registers in total
+# (more waves).  In the sweep it also removes the copies of the accumulators
+# between AGPRs and VGPRs that the AGPR form makes at every block column.
+FILE_FLAGS = {"kernels_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+              "kernels.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def sources():

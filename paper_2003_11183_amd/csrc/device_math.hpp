@@ -42,6 +42,11 @@ __device__ __forceinline__ const TLRQMC_GLOBAL T *as_global(const T *p) {
   return (const TLRQMC_GLOBAL T *)p;
 }
 
+// Word 3 of a raw buffer resource (data format 32, every other field zero);
+// loads through it take byte offsets, and an offset past the resource's
+// byte count reads zero.
+constexpr int kRawBufferWord3 = 0x00020000;
+
 // Copy of a wave-uniform descriptor in device memory, read with scalar
 // loads (T is a plain struct of 8-byte multiples).
 template <class T>

@@ -92,14 +92,14 @@ __global__ __launch_bounds__(256) void k_init_batch(const InitParams *ps) {
 // Rows of earlier blocks enter through FP64 matrix cores: for row block q a
 // wave forms C(64 samples x 16 rows) = sum_{p<q} Y_p(64 x 16) B(q,p)^T with
 // v_mfma_f64_16x16x4_f64, four 16-sample tiles side by side.  The A operand
-// is y of this wave's samples (lane l: sample 16*tile + l%16, block column
-// 4*kstep + l/16), the B operand is the factor block read once per k-step
-// (lane l: entry [(4*kstep + l/16)*16 + l%16], contiguous).  The result
-// leaves the matrix layout through a wave-private LDS tile (two halves of
-// 32 samples) into the per-lane accumulator.  Every lane of a wave takes
-// part; lanes past the chunk's end compute on clamped indices and store
-// nothing outside their own Y column, which lies inside the leading
-// dimension.
+// is y of this wave's samples (lane l: sample 4*(l%16) + tile, block column
+// 4*kstep + l/16, so that a lane's four tiles are four consecutive samples),
+// the B operand is the factor block read once per k-step (lane l: entry
+// [(4*kstep + l/16)*16 + l%16], contiguous).  The result leaves the matrix
+// layout through a wave-private LDS tile (two halves of 32 samples) into the
+// per-lane accumulator.  Every lane of a wave takes part; lanes past the
+// chunk's end compute on clamped indices and store nothing outside their own
+// Y column, which lies inside the leading dimension.
 __device__ const double kNoDelta64 = 0.0;
 __device__ const float kNoDelta32 = 0.0f;
 
@@ -130,6 +130,11 @@ __device__ __forceinline__ void sweep_body(const SweepParams &p, int64_t si, dou
   const int lane = static_cast<int>(threadIdx.x) & 63;
   const int64_t w0 = si - lane;
   if (w0 >= p.count) return;  // whole wave past the end
+  // the same first sample, seen as wave-uniform (it keeps buffer resources
+  // built from it in scalar registers)
+  const int64_t w0u = static_cast<int64_t>(
+      (static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(w0 >> 32)))) << 32) |
+      static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(w0))));
   const bool live = si < p.count;
   const int64_t sl = live ? si : p.count - 1;
   const int64_t g = p.g0 + sl;
@@ -158,26 +163,68 @@ __device__ __forceinline__ void sweep_body(const SweepParams &p, int64_t si, dou
       f64x4 c[4];
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt) c[mt] = f64x4{0.0, 0.0, 0.0, 0.0};
-      const auto Bq = as_global(p.B + static_cast<int64_t>(q) * (q + 1) / 2 * SB * SB);
-      const auto Yw = as_global(static_cast<const DT *>(p.Y) + w0 + (lane & 15) + static_cast<int64_t>(lane >> 4) * ld);
+      // Tile mt's A row i is sample 4 i + mt of the wave, so that lane l
+      // reads samples 4 (l % 16) .. 4 (l % 16) + 3 of one y row in a single
+      // 16-byte (FP64: two 16-byte) load.  The operands of block column
+      // pb + 1 are loaded before the products of block column pb (the last
+      // column loads itself again), so their latency overlaps the matrix
+      // pipe.  The loads go through buffer resources over the block column
+      // (16 y rows of the wave's samples; the q factor blocks of row block
+      // q) with the k-step's offset in a scalar register; 16 ld elements
+      // stay below 2 GiB (the drivers bound ld by 2^22).
+      using V4 = DT __attribute__((ext_vector_type(4)));
+      const uint32_t y_lane = static_cast<uint32_t>((static_cast<int64_t>(lane >> 4) * ld + 4 * (lane & 15)) * sizeof(DT));
+      const uint32_t y_4rows = static_cast<uint32_t>(4 * ld * sizeof(DT));
+      const int y_bytes = static_cast<int>(SB * ld * sizeof(DT));
+      const double *Bq = p.B + static_cast<int64_t>(q) * (q + 1) / 2 * SB * SB;
+      const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(Bq), 0, q * SB * SB * 8, kRawBufferWord3);
+      auto load_col = [&](int pb, V4 (&ya)[4], double (&ba)[4]) {
+        const __amdgpu_buffer_rsrc_t ry = __builtin_amdgcn_make_buffer_rsrc(
+            static_cast<DT *>(p.Y) + w0u + static_cast<int64_t>(pb) * SB * ld, 0, y_bytes, kRawBufferWord3);
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const int so = static_cast<int>(ks * y_4rows);
+          if constexpr (PREC) {
+            ya[ks] = __builtin_bit_cast(V4, __builtin_amdgcn_raw_buffer_load_b128(ry, y_lane, so, 0));
+          } else {
+            typedef double f64x2 __attribute__((ext_vector_type(2)));
+            const f64x2 lo = __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(ry, y_lane, so, 0));
+            const f64x2 hi = __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(ry, y_lane + 16, so, 0));
+            ya[ks] = V4{lo[0], lo[1], hi[0], hi[1]};
+          }
+          ba[ks] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rb, lane * 8, (pb * SB * SB + ks * 64) * 8, 0));
+        }
+      };
+      auto products = [&](const V4 (&ya)[4], const double (&ba)[4]) {
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt)
+            c[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(static_cast<double>(ya[ks][mt]), ba[ks], c[mt], 0, 0, 0);
+      };
+      V4 ya[4], yc[4];
+      double ba[4], bc[4];
+      load_col(0, ya, ba);
       for (int pb = 0; pb < q; ++pb) {
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
-          const double bv = Bq[pb * SB * SB + ks * 64 + lane];
-          const auto Yr = Yw + static_cast<int64_t>(pb * SB + ks * 4) * ld;
-#pragma unroll
-          for (int mt = 0; mt < 4; ++mt)
-            c[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(static_cast<double>(Yr[mt * 16]), bv, c[mt], 0, 0, 0);
+          yc[ks] = ya[ks];
+          bc[ks] = ba[ks];
         }
+        load_col(min(pb + 1, q - 1), ya, ba);
+        products(yc, bc);
       }
       blk += static_cast<int64_t>(q) * SB * SB;
-      // matrix layout -> one lane per sample, 32 samples at a time
+      // matrix layout -> one lane per sample, 32 samples at a time (tile row
+      // i of tile mt is sample 4 i + mt; rows r = 2h, 2h + 1 of every tile
+      // hold samples 32 h .. 32 h + 31)
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
+        for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) tr[(mt * 16 + mfma64_row(lane, r)) * kTrLd + (lane & 15)] = c[2 * h + mt][r];
+          for (int r = 2 * h; r < 2 * h + 2; ++r)
+            tr[(4 * mfma64_row(lane, r) + mt - 32 * h) * kTrLd + (lane & 15)] = c[mt][r];
         __builtin_amdgcn_wave_barrier();
         if ((lane >> 5) == h) {
 #pragma unroll

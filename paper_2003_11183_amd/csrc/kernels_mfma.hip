@@ -117,7 +117,7 @@ __device__ __forceinline__ void lr_mfma_body(const MfmaLrParams &p, unsigned bid
     // keeps the resource scalar (the clamp would otherwise go to the VALU)
     const int bytes = __builtin_amdgcn_readfirstlane(static_cast<int>(max(0, min(32, p.K - kk)) * row_bytes));
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<TB *>(B) + static_cast<int64_t>(kk) * p.ld + s0, 0, bytes, 0x00020000);
+        const_cast<TB *>(B) + static_cast<int64_t>(kk) * p.ld + s0, 0, bytes, dev::kRawBufferWord3);
 #pragma unroll
     for (int u = 0; u < NS; ++u)
 #pragma unroll

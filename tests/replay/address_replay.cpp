@@ -190,10 +190,15 @@ void replay_sweep_factor(const SweepParams &p, bool tri, int64_t tile_doubles) {
           for (int lane = 0; lane < 64; ++lane)
             S.check_seg(p.B, seg, at(p.B, bq + pb * SB * SB + ks * 64 + lane), 8, "sweep factor block");
       blk += static_cast<int64_t>(q) * SB * SB;
+      // transposition in two halves: rows r = 2h, 2h + 1 of tile mt hold
+      // samples 16 r + 4 (l / 16) + mt
       for (int lane = 0; lane < 64; ++lane)
-        for (int mt = 0; mt < 2; ++mt)
-          for (int r = 0; r < 4; ++r)
-            if ((mt * 16 + lane / 16 + 4 * r) * kTrLd + (lane & 15) >= 32 * kTrLd) S.fail("sweep lds", 0, 8, "(index)");
+        for (int h = 0; h < 2; ++h)
+          for (int mt = 0; mt < 4; ++mt)
+            for (int r = 2 * h; r < 2 * h + 2; ++r) {
+              const int at_lds = (4 * (lane / 16 + 4 * r) + mt - 32 * h) * kTrLd + (lane & 15);
+              if (at_lds < 0 || at_lds >= 32 * kTrLd) S.fail("sweep lds", 0, 8, "(index)");
+            }
     }
     const int rows = std::min(SB, p.mj - q * SB);
     S.check_seg(p.B, seg, at(p.B, blk), 8, "sweep inverse diagonal");
@@ -241,10 +246,13 @@ void replay_sweep(const SweepParams &p, Grid g, bool two_sided, bool scaled, boo
       if (q > 0)
         for (int64_t pb : span(0, q))
           for (int64_t ks : span(0, 4))
-            for (int64_t mt : span(0, 4)) {
-              const int64_t yi = w0 + (lane & 15) + static_cast<int64_t>(lane >> 4) * p.ld +
-                                 (pb * SB + ks * 4) * p.ld + mt * 16;
-              S.check(p.Y, at_bytes(p.Y, yi * esz), esz, "sweep y (matrix cores)");
+            {
+              // one vector load of samples 4 (l % 16) .. 4 (l % 16) + 3
+              const int64_t yi = w0 + 4 * (lane & 15) + static_cast<int64_t>(lane >> 4) * p.ld +
+                                 (pb * SB + ks * 4) * p.ld;
+              const uint64_t a = at_bytes(p.Y, yi * esz);
+              if (a % (4 * esz) != 0) S.fail("sweep y (matrix cores)", a, 4 * esz, "(misaligned vector load)");
+              S.check(p.Y, a, 4 * esz, "sweep y (matrix cores)");
             }
       const int rows = std::min(SB, p.mj - q * SB);
       for (int t = 0; t < rows; ++t) {
