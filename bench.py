@@ -21,6 +21,7 @@ import argparse
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -45,8 +46,8 @@ PEAK_FP64_VALU = PEAK_FP64
 # minus the FMAs of the in-block row products.  Reported only while the
 # kernel sources have the digest they were measured on.
 CPHI = {
-    1: {"f64": 19.0, "f32": 82.5, "digest": "4927771132f664b2"},
-    0: {"f64": 355.0, "f32": 0.0, "digest": "4927771132f664b2"},
+    1: {"f64": 19.0, "f32": 82.5, "digest": "e072b3fb5191f925"},
+    0: {"f64": 355.0, "f32": 0.0, "digest": "e072b3fb5191f925"},
 }
 
 
@@ -76,6 +77,8 @@ def parse():
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--no-reorder-study", action="store_true",
                     help="skip the ordering study on the n = 4,096 MVN workload")
+    ap.add_argument("--issue-probe", action="store_true",
+                    help="only run the issue probe (paper_2003_11183_amd/probe): matrix-core waves beside vector waves")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (scale for HBM byte counters)")
     return ap.parse_args()
@@ -133,15 +136,30 @@ def kernel_work(kind: str, st: dict, n: int, m: int, precision: int) -> dict:
     return {"fp64_valu": float("nan"), "fp64_mfma": 0.0, "bf16_mfma": 0.0, "fp32_valu": 0.0, "bytes": 0.0}
 
 
+def issue_times(w: dict) -> dict:
+    """Time of one sample's work on each resource.  On MI355X an FP64
+    matrix-core instruction holds its SIMD for its whole duration: a vector
+    wave beside it on the same SIMD does not issue meanwhile (measured: a
+    wave of 8,192 FP32 or FP64 FMAs takes about 45,000 cycles alone and
+    176,000 beside a wave of 2,048 FP64 16x16x4 MFMAs, which take 131,000;
+    beside the same number of BF16 16x16x32 MFMAs it takes 57,000).  So the
+    FP64 products and the vector operations add up on one issue resource,
+    while BF16 products and HBM transfers run beside it."""
+    return {"fp64_mfma": w["fp64_mfma"] / PEAK_FP64,
+            "valu": w["fp64_valu"] / PEAK_FP64 + w["fp32_valu"] / PEAK_FP32,
+            "bf16_mfma": w["bf16_mfma"] / PEAK_BF16_MFMA,
+            "hbm": w["bytes"] / PEAK_HBM}
+
+
 def time_bound(w: dict) -> tuple[float, str]:
     """Lower bound on the time of one sample's work and the resource that
-    sets it: the matrix pipe (FP64 and BF16 products), the vector ALU (FP64
-    and FP32 operations) and HBM run side by side."""
-    t = {"mfma": w["fp64_mfma"] / PEAK_FP64 + w["bf16_mfma"] / PEAK_BF16_MFMA,
-         "alu": w["fp64_valu"] / PEAK_FP64 + w["fp32_valu"] / PEAK_FP32,
-         "hbm": w["bytes"] / PEAK_HBM}
+    sets it: the SIMD issue (FP64 products plus vector operations, named
+    "mfma" or "alu" after the larger part), the BF16 matrix pipe and HBM."""
+    it = issue_times(w)
+    simd = it["fp64_mfma"] + it["valu"]
+    t = {("mfma" if it["fp64_mfma"] >= it["valu"] else "alu"): simd, "bf16": it["bf16_mfma"], "hbm": it["hbm"]}
     b = max(t, key=t.get)
-    return t[b], b
+    return t[b], ("mfma" if b == "bf16" else b)
 
 
 def time_form(T, ctx, F, c, precision, steps, warmup):
@@ -172,24 +190,37 @@ def time_form(T, ctx, F, c, precision, steps, warmup):
 # only while the kernel sources and the build script (its device flags) still
 # have the digest it was measured on.
 TRAFFIC = {
-    (3, "sweep", 1): {"bytes_per_launch": 1.938e9, "digest": "4927771132f664b2"},
-    (3, "delta", 1): {"bytes_per_launch": 4.272e8, "digest": "4927771132f664b2"},
-    (3, "zproj", 1): {"bytes_per_launch": 4.274e8, "digest": "4927771132f664b2"},
-    (3, "sweep", 0): {"bytes_per_launch": 3.860e9, "digest": "4927771132f664b2"},
-    (3, "delta", 0): {"bytes_per_launch": 1.304e9, "digest": "4927771132f664b2"},
-    (3, "zproj", 0): {"bytes_per_launch": 2.414e9, "digest": "4927771132f664b2"},
+    (3, "sweep", 1): {"bytes_per_launch": 1.938e9, "digest": "e072b3fb5191f925"},
+    (3, "delta", 1): {"bytes_per_launch": 4.272e8, "digest": "e072b3fb5191f925"},
+    (3, "zproj", 1): {"bytes_per_launch": 4.274e8, "digest": "e072b3fb5191f925"},
+    (3, "sweep", 0): {"bytes_per_launch": 3.860e9, "digest": "e072b3fb5191f925"},
+    (3, "delta", 0): {"bytes_per_launch": 1.304e9, "digest": "e072b3fb5191f925"},
+    (3, "zproj", 0): {"bytes_per_launch": 2.414e9, "digest": "e072b3fb5191f925"},
 }
 KERNEL_SOURCES = tuple(os.path.join("csrc", f) for f in (
     "kernels.hip", "kernels_mfma.hip", "kernels_lr64.hip", "device_math.hpp", "special_tables.hpp",
-    "internal.hpp", "plan.hpp")) + ("build.py",)
+    "internal.hpp", "plan.hpp"))
+
+
+def device_options() -> str:
+    """The device compiler options of the kernel files (the build script's
+    common and per-file flags, without include paths, which differ between
+    machines)."""
+    from paper_2003_11183_amd import build
+    common = [a for a in build.DEVICE[1:] if not a.startswith("-I")]
+    per_file = sorted((f, tuple(v)) for f, v in build.FILE_FLAGS.items())
+    return repr((common, per_file))
 
 
 def kernel_digest() -> str:
+    """Digest of what the measured kernels are built from: their sources
+    and the device compiler options."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2003_11183_amd", f), "rb") as fh:
             h.update(fh.read())
+    h.update(device_options().encode())
     return h.hexdigest()[:16]
 
 
@@ -207,9 +238,13 @@ def kind_figures(kind, w, samples_per_launch, avg_s, tr):
     out = {"bound": bound, "frac": frac, "peak": peak, "achieved": frac * peak,
            "unit": "GB/s" if bound == "hbm" else "TFLOP/s", "avg_launch_ms": 1e3 * avg_s,
            "lower_bound_ms": 1e3 * t_launch,
+           "lower_bound_parts_ms": {k: 1e3 * v * samples_per_launch for k, v in issue_times(w).items()},
            "alg_bytes_per_launch": w["bytes"] * samples_per_launch,
            "alg_hbm_tb_per_s": w["bytes"] * samples_per_launch / avg_s / 1e12,
            "traffic": tr, "hbm_tb_per_s": (tr / avg_s / 1e12) if tr else None}
+    if bound != "hbm" and w["bf16_mfma"] == 0:
+        # the FP64 products and vector operations share the SIMD's issue
+        out["peak_note"] = "FP64 matrix products and vector operations add on the SIMD issue; achieved is their FP64-equivalent rate"
     if kind == "sweep":
         # the exact row products alone, every flop priced at the FP64 peak
         out["frac_rows_only"] = w["rows"] * samples_per_launch / PEAK_FP64 / avg_s
@@ -310,6 +345,11 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(sharding across GPUs is designed, not built)"}))
         sys.exit(2)
+    if args.issue_probe:
+        probe = os.path.join(ROOT, "paper_2003_11183_amd", "probe", "issue_probe")
+        if not os.path.exists(probe):
+            sys.exit("the issue probe is not built: python -m paper_2003_11183_amd.build")
+        sys.exit(subprocess.run([probe]).returncode)
     import torch
     if args.copy_calibration > 0:
         copy_calibration(torch, args.copy_calibration)

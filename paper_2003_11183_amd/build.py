@@ -78,7 +78,25 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}")
     os.replace(tmp, LIB)
+    build_probe(verbose)
     return LIB
+
+
+PROBE_SRC = os.path.join(PKG, "probe", "issue_probe.hip")
+PROBE = os.path.join(PKG, "probe", "issue_probe")
+
+
+def build_probe(verbose: bool = False) -> str:
+    """The issue probe behind bench.py's roofline model (an executable of
+    its own, not part of the library): ``python bench.py --issue-probe``."""
+    cmd = DEVICE + [PROBE_SRC, "-o", PROBE + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"issue probe build failed:\n{r.stdout}")
+    os.replace(PROBE + ".tmp", PROBE)
+    return PROBE
 
 
 if __name__ == "__main__":
