@@ -76,3 +76,15 @@ def test_traffic_table_keys():
     for (cfg, kind, prec), e in bench.TRAFFIC.items():
         assert cfg in (1, 2, 3, 4) and kind in kinds and prec in (0, 1)
         assert e["bytes_per_launch"] > 0 and len(e["digest"]) == 16
+
+
+def test_ratio_note_sums_the_lower_bounds():
+    roof = {"kinds": {"sweep": {"lower_bound_ms": 0.2, "frac": 0.4}, "delta": {"lower_bound_ms": 0.05, "frac": 0.2},
+                      "zproj": {"lower_bound_ms": 0.05, "frac": 0.1}}}
+    fp64 = {"roofline": {"kinds": {"sweep": {"lower_bound_ms": 0.4, "frac": 0.3},
+                                   "delta": {"lower_bound_ms": 0.35, "frac": 0.2},
+                                   "zproj": {"lower_bound_ms": 0.35, "frac": 0.2}}}}
+    r = bench.ratio_note(roof, fp64)
+    assert abs(r["ratio_at_resource_bounds"] - 1.1 / 0.3) < 1e-12
+    assert r["fp64_form_frac"]["sweep"] == 0.3 and r["precision_form_frac"]["zproj"] == 0.1
+    assert bench.ratio_note(roof, None) is None
