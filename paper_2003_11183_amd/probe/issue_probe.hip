@@ -19,13 +19,15 @@ namespace {
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kIters = 2048;   // FMAs per chain of a vector wave
 constexpr int kBlocks = 256;   // one work-group per CU
 constexpr int kThreads = 512;  // eight waves: two per SIMD
 
 // MODE: 0 nothing, 1 FP64 16x16x4 MFMA, 2 BF16 16x16x32 MFMA, 3 FP64 vector
-// FMAs (kIters / 4 matrix instructions per chain, four chains).
+// FMAs, 4 INT8 16x16x64 MFMA (kIters / 4 matrix instructions per chain,
+// four chains).
 // V64: the vector waves run FP64 (true) or FP32 (false) FMAs.
 template <int MODE, bool V64>
 __global__ __launch_bounds__(kThreads) void k_probe(float a, double ad, float *out, long long *cyc) {
@@ -49,6 +51,13 @@ __global__ __launch_bounds__(kThreads) void k_probe(float a, double ad, float *o
 #pragma unroll
         for (int m = 0; m < 4; ++m) c[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c[m], 0, 0, 0);
       r = c[0][0] + c[1][1] + c[2][2] + c[3][3];
+    } else if constexpr (MODE == 4) {
+      i32x4 c[4] = {};
+      i32x4 x = {t, 1, 2, 3}, y = {3, 2, 1, t};
+      for (int it = 0; it < kIters / 4; ++it)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) c[m] = __builtin_amdgcn_mfma_i32_16x16x64_i8(x, y, c[m], 0, 0, 0);
+      r = static_cast<float>(c[0][0] + c[1][1] + c[2][2] + c[3][3]);
     } else if constexpr (MODE == 3) {
       double x0 = t * 1e-9, x1 = x0 + 1, x2 = x0 + 2, x3 = x0 + 3;
       for (int it = 0; it < kIters; ++it) {
@@ -121,10 +130,12 @@ int main() {
   run<1, false>("512 x 4 FP64 16x16x4 MFMA", out, cyc);
   run<2, false>("512 x 4 BF16 16x16x32 MFMA", out, cyc);
   run<3, false>("4 x 2048 FP64 vector FMAs", out, cyc);
+  run<4, false>("512 x 4 INT8 16x16x64 MFMA", out, cyc);
   run<0, true>("nothing", out, cyc);
   run<1, true>("512 x 4 FP64 16x16x4 MFMA", out, cyc);
   run<2, true>("512 x 4 BF16 16x16x32 MFMA", out, cyc);
   run<3, true>("4 x 2048 FP64 vector FMAs", out, cyc);
+  run<4, true>("512 x 4 INT8 16x16x64 MFMA", out, cyc);
   check(hipFree(out), "free");
   check(hipFree(cyc), "free");
   return 0;
