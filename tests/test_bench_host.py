@@ -88,3 +88,14 @@ def test_ratio_note_sums_the_lower_bounds():
     assert abs(r["ratio_at_resource_bounds"] - 1.1 / 0.3) < 1e-12
     assert r["fp64_form_frac"]["sweep"] == 0.3 and r["precision_form_frac"]["zproj"] == 0.1
     assert bench.ratio_note(roof, None) is None
+
+
+def test_kernel_digest_follows_device_options_not_paths(monkeypatch):
+    from paper_2003_11183_amd import build
+    d0 = bench.kernel_digest()
+    # include paths differ between machines: not part of the digest
+    monkeypatch.setattr(build, "DEVICE", build.DEVICE + ["-I/somewhere/else"])
+    assert bench.kernel_digest() == d0
+    # a device option of a kernel file is
+    monkeypatch.setattr(build, "FILE_FLAGS", dict(build.FILE_FLAGS, **{"kernels.hip": []}))
+    assert bench.kernel_digest() != d0
